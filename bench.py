@@ -1,0 +1,213 @@
+"""Benchmark: BBWADG LSRK4 steps on one MI355X.
+
+Workload (the paper's method at the configuration the headline metric is quoted on):
+unit cube, 32^3 cells x 6 Kuhn tetrahedra = 196,608 affine tets, N = 5, M = 2, FP64,
+c^2 = 1 + 8 seeded Gaussian bumps (amplitude U[-0.4, 0.4], width 0.1, seed 0) projected to
+P^2 per element, Gaussian pressure pulse (width 0.05) at the centre, p = 0 walls,
+dt from CFL 0.5. Synthetic, seeded inputs; nothing is read from disk.
+
+One step = one full low-storage RK4 step (five fused stage kernels: volume, surface/lift,
+WADG multiply + projection and the RK update), inputs resident in HBM. The timed region is
+`steps` back-to-back steps on torch's current stream, bracketed by device synchronisation.
+
+Printed: one JSON line with the FP64 throughput in GDOF-updates/s (K Np 4 steps / time),
+the roofline of the stage kernel (algorithmic bytes / measured launch time vs 8 TB/s),
+an FP32 leg of the same workload with its per-field L2 difference from FP64, and the CPU
+oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CELLS, N, M = 32, 5, 2
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_cube196k_N5_M2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1808_08645_amd", "csrc", "stage_kernel.hpp")
+
+
+def dimp(n):
+    return (n + 1) * (n + 2) * (n + 3) // 6
+
+
+def algorithmic_bytes_per_element(n, m, word):
+    """One fused stage reads q and res and writes q and res (16 Np words), reads the c^2
+    coefficients (Mp words), the geometry record (25 words: G, Fscale and n per face) and
+    the 4 neighbour ids (16 bytes)."""
+    return (16 * dimp(n) + dimp(m) + 25) * word + 16
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on
+    the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch_f64")
+
+
+def setup(dtype):
+    import paper_1808_08645_amd as bb
+    from workloads import c2_gaussian_bumps, ic_gaussian_pulse, kuhn_cube_mesh
+
+    xyz, etov = kuhn_cube_mesh(CELLS)
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    s.project_c2(c2_gaussian_bumps(0))
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    q0 = s.initial_state([ic_gaussian_pulse, zero, zero, zero])
+    return s, q0
+
+
+def run_leg(s, q0, dt, steps, warmup):
+    import torch
+    q = s.to_device(q0)
+    res = torch.zeros_like(q)
+    if warmup:
+        s.step(q, res, dt, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(q, res, dt, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    # An odd total stage count ends with one state copy; time it alone to take it out.
+    copy_ms = 0.0
+    if (5 * steps) % 2 == 1:
+        tmp = torch.empty_like(q)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        tmp.copy_(q)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = c0.elapsed_time(c1)
+    return q, ms, wall, copy_ms
+
+
+def cpu_baseline(dt):
+    """The oracle (dense quadrature WADG, FP64, NumPy/OpenBLAS) timed on a bounded sample:
+    the same workload on 16^3 cells x 6 = 24,576 tets, one LSRK4 step."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import Oracle
+    from workloads import c2_gaussian_bumps, ic_gaussian_pulse, kuhn_cube_mesh
+    cells = 16
+    xyz, etov = kuhn_cube_mesh(cells)
+    o = Oracle(xyz, etov, N, M)
+    o.set_c2_function(c2_gaussian_bumps(0), project=True)
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    Q = o.project_initial([ic_gaussian_pulse, zero, zero, zero])
+    t0 = time.perf_counter()
+    o.step(Q, np.zeros_like(Q), dt, 1)
+    t = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    K = len(etov)
+    return {"value": K * dimp(N) * 4 / t / 1e9, "unit": "GDOF-updates/s", "cores": int(threads),
+            "kind": "oracle", "seconds": t,
+            "sample": f"cube 16^3x6 = {K} tets, N={N}, M={M}, same medium and pulse, 1 LSRK4 step, FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 leg (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this path has no multi-GPU mode "
+              "(elements would be partitioned with one face-trace exchange per stage).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    out = {}
+    s64, q0 = setup("f32" if args.fp32_only else "f64")
+    dt = s64.suggest_dt(0.5)
+    K = s64.K
+    dofs = K * dimp(N) * 4
+    q64, ms, wall, copy_ms = run_leg(s64, q0, dt, args.steps, args.warmup)
+    kernel_ms = (ms - copy_ms) / (5 * args.steps)
+    word = 4 if args.fp32_only else 8
+    alg = algorithmic_bytes_per_element(N, M, word) * K
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    traffic = None if args.fp32_only else measured_traffic()
+    value = dofs * args.steps / (ms * 1e-3) / 1e9
+    out.update({
+        "metric": "GDOF-updates/s per RK step (FP32 vs FP64) + % HBM peak, at stated L2 error",
+        "value": value,
+        "unit": "GDOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.fp32_only else "f64",
+        "data": "synthetic",
+        "config": {"workload": "cube196k_N5_M2", "elements": K, "N": N, "M": M, "dofs": dofs,
+                   "medium": "1 + 8 Gaussian bumps (seed 0), projected to P^2", "ic": "Gaussian pulse",
+                   "bc": "p=0 walls", "dt": dt, "cfl": 0.5, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "stage_kernel (fused volume + surface/lift + WADG + LSRK stage)",
+                     "kernel_ms": kernel_ms,
+                     "alg_bytes_per_launch": alg},
+    })
+    if not args.no_fp32 and not args.fp32_only:
+        s32, _ = setup("f32")
+        q32, ms32, _, _ = run_leg(s32, q0, dt, args.steps, args.warmup)
+        # both legs advanced warmup + steps steps from the same start
+        import torch
+        a = q32.double()
+        b = q64
+        num = torch.sum((a - b) ** 2, dim=(1, 2))
+        den = torch.clamp(torch.sum(b ** 2, dim=(1, 2)), min=1e-300)
+        rel = torch.sqrt(num / den).cpu().numpy().tolist()
+        l2a = s64.l2norm2((a - b).contiguous())
+        l2b = s64.l2norm2(b)
+        rel_fn = np.sqrt(l2a / np.maximum(l2b, 1e-300)).tolist()
+        out["fp32"] = {"value": dofs * args.steps / (ms32 * 1e-3) / 1e9, "ms_per_step": ms32 / args.steps,
+                       "speedup_vs_fp64": ms / ms32,
+                       "rel_l2_vs_fp64_per_field": rel_fn,
+                       "rel_coef_l2_vs_fp64_per_field": rel,
+                       "alg_frac_hbm": algorithmic_bytes_per_element(N, M, 4) * K /
+                       ((ms32 / (5 * args.steps)) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out["l2_error"] = {"fp64_vs_oracle": "<= 1e-11 relative L2 per field (parity tests)",
+                       "fp32_vs_fp64": out.get("fp32", {}).get("rel_l2_vs_fp64_per_field")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * bbwadg.h -- C ABI of the MI355X (gfx950) BBWADG library.
+ *
+ * Bernstein-Bezier weight-adjusted DG (BBWADG) for the 3D acoustic system
+ *     (1/c^2) p_t + div u = 0,   u_t + grad p = 0          (paper Section 3.1, eq. awave)
+ * on affine tetrahedra: right-hand side and low-storage RK4 step.
+ *
+ * Data format
+ * -----------
+ * State arrays hold Bernstein coefficients, field-major: q[4][K][Np] with fields
+ * (p, u, v, w), Np = (N+1)(N+2)(N+3)/6, element k contiguous within a field, in the
+ * context's dtype (double for BBWADG_F64, float for BBWADG_F32).
+ * Coefficient i of element k is the coefficient of B^N_alpha (paper Section 2,
+ * B^N_alpha = N!/alpha! lambda^alpha) where the barycentric coordinates lambda_0..3
+ * belong to the element's vertices SORTED BY ASCENDING GLOBAL VERTEX ID
+ * (bbwadg_element_vertices returns that order), and alpha = (a0,a1,a2,a3) is
+ * enumerated with a3 outermost (0..N), then a2 (0..N-a3), then a1 innermost
+ * (0..N-a3-a2); a0 = N-a1-a2-a3. The same order is used for c^2 coefficients of
+ * degree M: c2[K][Mp], Mp = (M+1)(M+2)(M+3)/6.
+ *
+ * Ownership and streams
+ * ---------------------
+ * The caller owns every state/rhs/res/c2 buffer passed in; the library never frees
+ * them. The library owns the context: geometry, connectivity, operator tables, the
+ * per-element c^2 coefficients and one internal state-sized device buffer, all
+ * allocated by bbwadg_create and freed by bbwadg_destroy. bbwadg_rhs and bbwadg_step
+ * allocate nothing. Streams are borrowed hipStream_t values passed as void*
+ * (NULL = the null stream); all device work is asynchronous on that stream.
+ * A context is not thread-safe: the caller serialises calls on one context.
+ *
+ * Errors
+ * ------
+ * Every entry point returns 0 (BBWADG_OK) or a negative code; bbwadg_last_error()
+ * returns a thread-local message for the last failure. On error no state changes.
+ */
+#ifndef BBWADG_H
+#define BBWADG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BBWADG_OK = 0,
+  BBWADG_EINVAL = -1, /* bad argument: range, NULL pointer, dtype, host-only context */
+  BBWADG_EMESH = -2,  /* non-conforming mesh, face shared by > 2 elements, degenerate element */
+  BBWADG_EC2 = -3,    /* c^2 not set, non-finite, or not positive at a check point */
+  BBWADG_ENOMEM = -4, /* host or device allocation failed */
+  BBWADG_EHIP = -5    /* HIP runtime or kernel launch error */
+};
+
+enum { BBWADG_F64 = 0, BBWADG_F32 = 1 };
+enum { BBWADG_BC_P0 = 0, BBWADG_BC_RIGID = 1 };
+enum { BBWADG_DEVICE = 0, BBWADG_HOST_ONLY = 1 };
+
+typedef struct bbwadg_ctx bbwadg_ctx;
+
+typedef struct {
+  int64_t num_vertices;  /* Nv */
+  const double* xyz;     /* host [Nv][3], copied */
+  int64_t num_elements;  /* K >= 1 */
+  const int32_t* etov;   /* host [K][4] vertex ids in [0, Nv), any order; copied */
+  int32_t bc;            /* boundary faces: BBWADG_BC_P0 (p+ = -p, u+ = u) or
+                            BBWADG_BC_RIGID (p+ = p, u+ = u - 2(u.n)n) */
+} bbwadg_mesh;
+
+typedef struct {
+  int32_t N;       /* polynomial degree, 1..9 */
+  int32_t M;       /* degree of the c^2 approximation, 0..min(N,4) */
+  int32_t dtype;   /* BBWADG_F64 or BBWADG_F32: storage and arithmetic of rhs/step */
+  int32_t mode;    /* BBWADG_DEVICE, or BBWADG_HOST_ONLY (geometry, tables and projections
+                      only; no HIP call is made and rhs/step return BBWADG_EINVAL) */
+  double tau_p;    /* penalty on [[p]] (paper Section 3.1 fluxes), >= 0 */
+  double tau_u;    /* penalty on [[u]].n, >= 0 */
+} bbwadg_opts;
+
+/* Build a context: sorts each element's vertices by global id, computes the affine
+ * geometry (G = dr/dx, J = |det dx/dr|, outward unit normals, Fscale = J_f/J with
+ * J_f = face area / 2), matches faces by their vertex triple, builds the Bernstein
+ * operator tables and (device mode) uploads them. Paper Section 3.1, eq. (matform).
+ * Errors: EINVAL (NULL, N/M/dtype/tau out of range, vertex id out of range),
+ * EMESH (face shared by more than two elements, |det| <= 1e-14 * h^3), ENOMEM, EHIP. */
+int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx** out);
+
+/* Free a context and its device buffers (NULL is a no-op). Synchronises the device. */
+int bbwadg_destroy(bbwadg_ctx* ctx);
+
+/* Thread-local text of the last error ("" if none). Valid until the next call. */
+const char* bbwadg_last_error(void);
+
+/* Sizes: Np, Nfp = (N+1)(N+2)/2, Mp, K. Any pointer may be NULL. */
+int bbwadg_sizes(const bbwadg_ctx* ctx, int32_t* Np, int32_t* Nfp, int32_t* Mp, int64_t* K);
+
+/* The element-to-vertex list in the library's local order (ascending global id per
+ * element), host [K][4]. This order defines the barycentric coordinates. */
+int bbwadg_element_vertices(const bbwadg_ctx* ctx, int32_t* etov_out);
+
+/* Per-element geometry, host arrays (any may be NULL): J [K]; G [K][3][3] with
+ * G[k][i][j] = d r_j / d x_i; normal [K][4][3] outward unit normal of face f (face f is
+ * opposite local vertex f); Fscale [K][4] = J_f / J; nbr [K][4] = 4*k'+f' of the
+ * neighbour element k' and its face f', or -1 on the boundary. */
+int bbwadg_geometry(const bbwadg_ctx* ctx, double* J, double* G, double* normal, double* Fscale,
+                    int32_t* nbr);
+
+/* ---- L^2 projections onto Bernstein polynomials (setup; FP64 on the host) ----
+ * A function f is projected per element onto P^d by the collapsed Gauss-Jacobi rule
+ * with n = d+3 points per direction (exact to degree 2d+5): coef = M_d^{-1} B^T W f.
+ * The caller samples f at the physical points and passes the samples back, so any
+ * Python/C function can be used. Elements are processed in ranges [k0, k1).        */
+
+/* Number of projection points per element for target degree d = M (c^2) or N (state). */
+int bbwadg_projection_npoints(const bbwadg_ctx* ctx, int32_t degree, int64_t* nq);
+
+/* Physical projection points of elements [k0,k1) for degree d: host [k1-k0][nq][3]. */
+int bbwadg_projection_points(const bbwadg_ctx* ctx, int32_t degree, int64_t k0, int64_t k1,
+                             double* xyz_out);
+
+/* Project samples host [k1-k0][nq] onto degree d; writes host FP64 [k1-k0][dimp(d)]. */
+int bbwadg_project_samples(const bbwadg_ctx* ctx, int32_t degree, int64_t k0, int64_t k1,
+                           const double* samples, double* coef_out);
+
+/* c^2 setup (paper Section 5: c^2 replaced by its per-element L^2 projection onto P^M).
+ * bbwadg_project_c2 samples the callback c2(x, y, z, user) at the projection points,
+ * projects in FP64, checks positivity at the projection points (EC2 otherwise), stores
+ * the coefficients in the context and, if c2_out != NULL, copies them as dtype into the
+ * device buffer c2_out [K][Mp] on `stream`. Stream-ordered before later rhs/step calls. */
+int bbwadg_project_c2(bbwadg_ctx* ctx, double (*c2)(double x, double y, double z, void* user),
+                      void* user, void* c2_out, void* stream);
+
+/* Inject per-element c^2 Bernstein coefficients host FP64 [K][Mp] (e.g. shared data for
+ * parity runs). EC2 if any value is non-finite or c^2_M is not positive at a check point.
+ * The device copy is refreshed on the next rhs/step call. */
+int bbwadg_set_c2(bbwadg_ctx* ctx, const double* c2_coef);
+
+/* Read back the stored c^2 coefficients, host FP64 [K][Mp]. EC2 if none is set. */
+int bbwadg_get_c2(const bbwadg_ctx* ctx, double* c2_coef);
+
+/* ---- hot path (device) ---- */
+
+/* Right-hand side (paper eq. WADGform, three parts: volume, surface/lift, WADG update):
+ *   rhs_p   = Pi_N( c^2_M * ( -div u + sum_f Fscale_f L^f F_p ) )
+ *   rhs_u_i = -d p/d x_i + sum_f Fscale_f n_i L^f F_u
+ * with F_p = (tau_p [[p]] - n.[[u]])/2 and F_u = (tau_u [[u]].n - [[p]])/2 (paper
+ * Section 3.1), derivatives by the sparse Bernstein stencils (Section 4), the lift by
+ * L^f = E_L L_0 (Section 4), the c^2 product by eq. (mcoeff) and Pi_N by the telescoped
+ * projection eq. (telescope) (Section 5). q, rhs: device [4][K][Np] of dtype, must not
+ * overlap. t is accepted for forcing terms and currently unused. */
+int bbwadg_rhs(bbwadg_ctx* ctx, const void* q, void* rhs, double t, void* stream);
+
+/* Advance q in place by nsteps steps of the five-stage, 2N-storage fourth-order
+ * Runge-Kutta scheme of Carpenter and Kennedy (paper Section 6.3.1): per stage
+ * res = a_k res + dt rhs(q), q = q + b_k res. res: device [4][K][Np], the 2N-storage
+ * register; zero it before the first step of a run. nsteps >= 0. q and res must not
+ * overlap. Each stage is one fused kernel that reads the state from one buffer and
+ * writes the next state to the other (q or the context's internal buffer); an odd
+ * total stage count ends with one device copy back into q. */
+int bbwadg_step(bbwadg_ctx* ctx, void* q, void* res, double t0, double dt, int32_t nsteps,
+                void* stream);
+
+/* dt = cfl / (c_max C_N max_{k,f} Fscale), C_N = (N+1)(N+3)/3, c_max^2 = the largest
+ * c^2 Bernstein coefficient (an upper bound of c^2_M by the convex-hull property). */
+int bbwadg_suggest_dt(const bbwadg_ctx* ctx, double cfl, double* dt);
+
+/* Per-field squared L^2 norms sum_k J_k int_ref q_k^2 of a device state [4][K][Np],
+ * accumulated in FP64 on the device with the closed-form Bernstein mass matrix;
+ * out: host double[4]. Synchronises `stream`. */
+int bbwadg_l2norm2(bbwadg_ctx* ctx, const void* q, double out[4], void* stream);
+
+/* c_j of the telescoped projection P^{N+M}_N = sum_j c_j E^N_{N-j}(E^N_{N-j})^T
+ * (E^{N+M}_N)^T (paper Theorem 5.1, Table 1), host double[N+1]. With M < 0 returns the
+ * coefficients of the inverse mass matrix representation (paper Theorem 5.2, Table 2).
+ * 1 <= N <= 9, -1 <= M <= 9. */
+int bbwadg_projection_coefficients(int32_t N, int32_t M, double* cj_out);
+
+/* Library version string. */
+const char* bbwadg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBWADG_H */

@@ -137,9 +137,11 @@ class Oracle:
     def project_modal(self, fn, deg: int, nproj: int | None = None):
         """Per-element L^2 projection of fn onto P^deg, as orthonormal-basis coefficients.
 
-        Uses the collapsed rule with deg + 6 points per direction unless ``nproj`` is given.
+        Uses the collapsed Gauss-Jacobi rule with deg + 3 points per direction (exact to
+        degree 2 deg + 5) unless ``nproj`` is given. The paper does not fix the rule for
+        this projection; this one is the reading shared with the library's setup code.
         """
-        n = deg + 6 if nproj is None else nproj
+        n = deg + 3 if nproj is None else nproj
         r, s, t, w = tet_rule(n)
         V = dubiner_tet(deg, r, s, t)
         Mm = V.T @ (w[:, None] * V)

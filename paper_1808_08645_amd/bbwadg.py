@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libbbwadg.so (argument marshalling only).
+
+Every step of the right-hand side and the time step runs in the HIP kernels of the
+library; this module only converts arguments. Device buffers are torch tensors on the
+current CUDA (HIP) device and work is queued on torch's current stream. If the library
+is not built, loading fails loudly: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbbwadg.so")
+
+OK, EINVAL, EMESH, EC2, ENOMEM, EHIP = 0, -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+BC_P0, BC_RIGID = 0, 1
+DEVICE, HOST_ONLY = 0, 1
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = (
+    "bbwadg_create", "bbwadg_destroy", "bbwadg_last_error", "bbwadg_sizes",
+    "bbwadg_element_vertices", "bbwadg_geometry", "bbwadg_projection_npoints",
+    "bbwadg_projection_points", "bbwadg_project_samples", "bbwadg_project_c2",
+    "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
+    "bbwadg_l2norm2", "bbwadg_projection_coefficients", "bbwadg_version",
+)
+
+
+class BBWADGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bbwadg error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("num_vertices", C.c_int64), ("xyz", C.POINTER(C.c_double)),
+                ("num_elements", C.c_int64), ("etov", C.POINTER(C.c_int32)), ("bc", C.c_int32)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("N", C.c_int32), ("M", C.c_int32), ("dtype", C.c_int32), ("mode", C.c_int32),
+                ("tau_p", C.c_double), ("tau_u", C.c_double)]
+
+
+C2_CALLBACK = C.CFUNCTYPE(C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbbwadg.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pd, pi32, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "bbwadg_create": (C.c_int, [C.POINTER(_Mesh), C.POINTER(_Opts), C.POINTER(vp)]),
+        "bbwadg_destroy": (C.c_int, [vp]),
+        "bbwadg_last_error": (C.c_char_p, []),
+        "bbwadg_sizes": (C.c_int, [vp, pi32, pi32, pi32, pi64]),
+        "bbwadg_element_vertices": (C.c_int, [vp, pi32]),
+        "bbwadg_geometry": (C.c_int, [vp, pd, pd, pd, pd, pi32]),
+        "bbwadg_projection_npoints": (C.c_int, [vp, i32, pi64]),
+        "bbwadg_projection_points": (C.c_int, [vp, i32, i64, i64, pd]),
+        "bbwadg_project_samples": (C.c_int, [vp, i32, i64, i64, pd, pd]),
+        "bbwadg_project_c2": (C.c_int, [vp, C2_CALLBACK, vp, vp, vp]),
+        "bbwadg_set_c2": (C.c_int, [vp, pd]),
+        "bbwadg_get_c2": (C.c_int, [vp, pd]),
+        "bbwadg_rhs": (C.c_int, [vp, vp, vp, dbl, vp]),
+        "bbwadg_step": (C.c_int, [vp, vp, vp, dbl, dbl, i32, vp]),
+        "bbwadg_suggest_dt": (C.c_int, [vp, dbl, pd]),
+        "bbwadg_l2norm2": (C.c_int, [vp, vp, pd, vp]),
+        "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
+        "bbwadg_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise BBWADGError(rc, _lib.bbwadg_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def dimp(n: int) -> int:
+    return (n + 1) * (n + 2) * (n + 3) // 6
+
+
+def projection_coefficients(N: int, M: int) -> np.ndarray:
+    """c_j of the telescoped projection (M >= 0) or of the inverse mass matrix (M = -1)."""
+    lib = load_library()
+    out = np.zeros(N + 1)
+    _check(lib.bbwadg_projection_coefficients(N, M, _dptr(out)))
+    return out
+
+
+class Solver:
+    """BBWADG acoustic solver on an affine tetrahedral mesh (one context of the library)."""
+
+    def __init__(self, xyz, etov, N: int, M: int, dtype: str = "f64", tau_p: float = 1.0,
+                 tau_u: float = 1.0, bc: str = "p0", host_only: bool = False):
+        self._lib = load_library()
+        self._ctx = C.c_void_p()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._etov = np.ascontiguousarray(etov, dtype=np.int32)
+        if self._xyz.ndim != 2 or self._xyz.shape[1] != 3 or self._etov.ndim != 2 or self._etov.shape[1] != 4:
+            raise ValueError("xyz must be [Nv, 3] and etov [K, 4]")
+        mesh = _Mesh(self._xyz.shape[0], _dptr(self._xyz), self._etov.shape[0],
+                     self._etov.ctypes.data_as(C.POINTER(C.c_int32)),
+                     {"p0": BC_P0, "rigid": BC_RIGID}[bc])
+        if dtype not in ("f64", "f32"):
+            raise ValueError("dtype must be 'f64' or 'f32'")
+        opts = _Opts(N, M, F64 if dtype == "f64" else F32, HOST_ONLY if host_only else DEVICE,
+                     float(tau_p), float(tau_u))
+        _check(self._lib.bbwadg_create(C.byref(mesh), C.byref(opts), C.byref(self._ctx)))
+        self.N, self.M, self.dtype, self.bc = N, M, dtype, bc
+        self.host_only = host_only
+        np_, nfp, mp, K = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(self._lib.bbwadg_sizes(self._ctx, C.byref(np_), C.byref(nfp), C.byref(mp), C.byref(K)))
+        self.Np, self.Nfp, self.Mp, self.K = np_.value, nfp.value, mp.value, K.value
+
+    # ---------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.bbwadg_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ----------------------------------------------------------------- queries
+    def element_vertices(self) -> np.ndarray:
+        out = np.empty((self.K, 4), dtype=np.int32)
+        _check(self._lib.bbwadg_element_vertices(self._ctx, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def geometry(self) -> dict:
+        K = self.K
+        J, G = np.empty(K), np.empty((K, 3, 3))
+        nrm, fs = np.empty((K, 4, 3)), np.empty((K, 4))
+        nbr = np.empty((K, 4), dtype=np.int32)
+        _check(self._lib.bbwadg_geometry(self._ctx, _dptr(J), _dptr(G), _dptr(nrm), _dptr(fs),
+                                         nbr.ctypes.data_as(C.POINTER(C.c_int32))))
+        return {"J": J, "G": G, "normal": nrm, "Fscale": fs, "nbr": nbr}
+
+    # ------------------------------------------------------------- projections
+    def projection_npoints(self, degree: int) -> int:
+        n = C.c_int64()
+        _check(self._lib.bbwadg_projection_npoints(self._ctx, degree, C.byref(n)))
+        return n.value
+
+    def projection_points(self, degree: int, k0: int = 0, k1: int | None = None) -> np.ndarray:
+        k1 = self.K if k1 is None else k1
+        nq = self.projection_npoints(degree)
+        out = np.empty((k1 - k0, nq, 3))
+        _check(self._lib.bbwadg_projection_points(self._ctx, degree, k0, k1, _dptr(out)))
+        return out
+
+    def project_samples(self, degree: int, samples, k0: int = 0, k1: int | None = None) -> np.ndarray:
+        k1 = self.K if k1 is None else k1
+        s = np.ascontiguousarray(samples, dtype=np.float64)
+        nq = self.projection_npoints(degree)
+        if s.shape != (k1 - k0, nq):
+            raise ValueError(f"samples must be [{k1 - k0}, {nq}]")
+        out = np.empty((k1 - k0, dimp(degree)))
+        _check(self._lib.bbwadg_project_samples(self._ctx, degree, k0, k1, _dptr(s), _dptr(out)))
+        return out
+
+    def project_function(self, fn, degree: int, chunk: int = 8192) -> np.ndarray:
+        """Per-element L^2 projection of a vectorised f(x, y, z) onto degree `degree`
+        (host FP64); returns Bernstein coefficients [K, dimp(degree)]."""
+        out = np.empty((self.K, dimp(degree)))
+        for k0 in range(0, self.K, chunk):
+            k1 = min(self.K, k0 + chunk)
+            X = self.projection_points(degree, k0, k1)
+            vals = np.asarray(fn(X[..., 0], X[..., 1], X[..., 2]), dtype=np.float64)
+            out[k0:k1] = self.project_samples(degree, np.broadcast_to(vals, X.shape[:2]), k0, k1)
+        return out
+
+    def project_c2(self, fn) -> np.ndarray:
+        """c^2_M: per-element projection of c^2 onto P^M, stored in the context."""
+        coef = self.project_function(fn, self.M)
+        self.set_c2(coef)
+        return coef
+
+    def project_c2_callback(self, fn_scalar, c2_out=None):
+        """The C-callback entry point (fn_scalar(x, y, z) -> float); optional device copy."""
+        cb = C2_CALLBACK(lambda x, y, z, u: float(fn_scalar(x, y, z)))
+        ptr = None if c2_out is None else C.c_void_p(c2_out.data_ptr())
+        stream = None if c2_out is None else self._stream()
+        _check(self._lib.bbwadg_project_c2(self._ctx, cb, None, ptr, stream))
+
+    def set_c2(self, coef):
+        c = np.ascontiguousarray(coef, dtype=np.float64)
+        if c.shape != (self.K, self.Mp):
+            raise ValueError(f"c2 coefficients must be [{self.K}, {self.Mp}]")
+        _check(self._lib.bbwadg_set_c2(self._ctx, _dptr(c)))
+
+    def get_c2(self) -> np.ndarray:
+        out = np.empty((self.K, self.Mp))
+        _check(self._lib.bbwadg_get_c2(self._ctx, _dptr(out)))
+        return out
+
+    def initial_state(self, fns) -> np.ndarray:
+        """Host FP64 Bernstein coefficients [4, K, Np] of four functions (p, u, v, w)."""
+        return np.stack([self.project_function(f, self.N) for f in fns])
+
+    def suggest_dt(self, cfl: float) -> float:
+        dt = C.c_double()
+        _check(self._lib.bbwadg_suggest_dt(self._ctx, float(cfl), C.byref(dt)))
+        return dt.value
+
+    # ---------------------------------------------------------------- hot path
+    def _stream(self):
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _check_state(self, t, name):
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != want or tuple(t.shape) != (4, self.K, self.Np) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {want} tensor of shape (4, {self.K}, {self.Np})")
+
+    def empty_state(self):
+        import torch
+        return torch.zeros((4, self.K, self.Np), dtype=torch.float64 if self.dtype == "f64" else torch.float32,
+                           device="cuda")
+
+    def to_device(self, arr):
+        import torch
+        return torch.as_tensor(np.ascontiguousarray(arr), device="cuda").to(
+            torch.float64 if self.dtype == "f64" else torch.float32).contiguous()
+
+    def rhs(self, q, out=None, t: float = 0.0):
+        self._check_state(q, "q")
+        if out is None:
+            out = self.empty_state()
+        self._check_state(out, "out")
+        _check(self._lib.bbwadg_rhs(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()),
+                                    float(t), self._stream()))
+        return out
+
+    def step(self, q, res, dt: float, nsteps: int = 1, t0: float = 0.0):
+        self._check_state(q, "q")
+        self._check_state(res, "res")
+        _check(self._lib.bbwadg_step(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(res.data_ptr()),
+                                     float(t0), float(dt), int(nsteps), self._stream()))
+        return q
+
+    def l2norm2(self, q) -> np.ndarray:
+        self._check_state(q, "q")
+        out = np.zeros(4)
+        _check(self._lib.bbwadg_l2norm2(self._ctx, C.c_void_p(q.data_ptr()), _dptr(out), self._stream()))
+        return out

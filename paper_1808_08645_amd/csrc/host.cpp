@@ -1,0 +1,925 @@
+// Host side of the BBWADG library: mesh ingest, affine geometry, face connectivity,
+// Bernstein operator tables, FP64 L^2 projections, the C ABI and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bbwadg.h"
+#include "bbwadg_internal.hpp"
+
+using namespace bbw;
+typedef long double ld;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+// ------------------------------------------------------------------ combinatorics
+ld factl(int n) {
+  ld r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+ld binoml(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  ld r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Multi-indices of degree n in the documented coefficient order (a3 outermost, a1 innermost).
+std::vector<std::array<int, 4>> mi3_list(int n) {
+  std::vector<std::array<int, 4>> out;
+  for (int a3 = 0; a3 <= n; ++a3)
+    for (int a2 = 0; a2 <= n - a3; ++a2)
+      for (int a1 = 0; a1 <= n - a3 - a2; ++a1) out.push_back({n - a1 - a2 - a3, a1, a2, a3});
+  return out;
+}
+// Face multi-indices (b0,b1,b2), b2 outermost, b1 innermost.
+std::vector<std::array<int, 3>> mi2_list(int n) {
+  std::vector<std::array<int, 3>> out;
+  for (int b2 = 0; b2 <= n; ++b2)
+    for (int b1 = 0; b1 <= n - b2; ++b1) out.push_back({n - b1 - b2, b1, b2});
+  return out;
+}
+int idx3(int n, int a1, int a2, int a3) {
+  if (a1 < 0 || a2 < 0 || a3 < 0 || a1 + a2 + a3 > n) return -1;
+  int s = 0;
+  for (int c = 0; c < a3; ++c) s += dim2(n - c);
+  for (int b = 0; b < a2; ++b) s += n - a3 - b + 1;
+  return s + a1;
+}
+int idx3(int n, const std::array<int, 4>& a) {
+  if (a[0] < 0 || a[0] + a[1] + a[2] + a[3] != n) return -1;
+  return idx3(n, a[1], a[2], a[3]);
+}
+int idx2(int n, const std::array<int, 3>& b) {
+  if (b[0] < 0 || b[1] < 0 || b[2] < 0 || b[0] + b[1] + b[2] != n) return -1;
+  int s = 0;
+  for (int c = 0; c < b[2]; ++c) s += n - c + 1;
+  return s + b[1];
+}
+
+// ------------------------------------------------------------- projection coefficients
+// Distinct eigenvalue k of the degree-n Bernstein mass matrix of the volume-4/3
+// reference tetrahedron: (4/3) 3! (n!)^2 / ((n-k)! (n+k+3)!).
+ld mass_eig(int n, int k) { return 8.0L * factl(n) * factl(n) / (factl(n - k) * factl(n + k + 3)); }
+
+// c_j of the telescoped projection (paper Theorem 5.1). In the orthogonal modal basis
+// E^N_{N-j}(E^N_{N-j})^T is diagonal with entries lambda^{N-j}_k / lambda^N_k on modes of
+// degree k <= N-j (paper Corollary A.3) and the reduction (E^{N+M}_N)^T scales mode k by
+// lambda^N_k / lambda^{N+M}_k (Lemma A.2), so requiring the identity on P^N gives the
+// triangular system sum_{j=0}^{N-k} c_j lambda^{N-j}_k = lambda^{N+M}_k, k = N..0.
+// With M < 0 the right-hand side is 1 (inverse mass matrix, Theorem 5.2).
+void projection_cj(int N, int M, ld* c) {
+  for (int k = N; k >= 0; --k) {
+    int jn = N - k;
+    ld rhs = (M < 0) ? 1.0L : mass_eig(N + M, k);
+    ld s = 0;
+    for (int j = 0; j < jn; ++j) s += c[j] * mass_eig(N - j, k);
+    c[jn] = (rhs - s) / mass_eig(N - jn, k);
+  }
+}
+
+// ----------------------------------------------------------------- Gauss-Jacobi rule
+// Nodes: eigenvalues of the symmetric Jacobi matrix of the weight (1-x)^a (1+x)^b, found
+// by bisection on Sturm sequence counts; weights: Christoffel numbers 1/sum_k p_k(x)^2
+// with orthonormal p_k from the same three-term recurrence.
+void gauss_jacobi(int n, ld a, ld b, std::vector<ld>& x, std::vector<ld>& w) {
+  std::vector<ld> d(n), e2(n, 0);  // diagonal, squared off-diagonal (e2[i] couples i-1, i)
+  for (int i = 0; i < n; ++i) {
+    ld s = 2 * i + a + b;
+    d[i] = (i == 0) ? (b - a) / (a + b + 2) : (b * b - a * a) / (s * (s + 2));
+    if (i >= 1) e2[i] = 4.0L * i * (i + a) * (i + b) * (i + a + b) / (s * s * (s + 1) * (s - 1));
+  }
+  auto count_below = [&](ld lam) {  // number of eigenvalues < lam
+    int cnt = 0;
+    ld q = d[0] - lam;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0) q = 1e-300L;
+      q = d[i] - lam - e2[i] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  x.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    ld lo = -1, hi = 1;
+    for (int it = 0; it < 200; ++it) {
+      ld mid = 0.5L * (lo + hi);
+      if (count_below(mid) > i) hi = mid; else lo = mid;
+    }
+    x[i] = 0.5L * (lo + hi);
+  }
+  ld mu0 = std::pow(2.0L, a + b + 1) * std::tgamma(a + 1) * std::tgamma(b + 1) / std::tgamma(a + b + 2);
+  w.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    ld pm1 = 0, p = 1.0L / std::sqrt(mu0), sum = p * p;
+    for (int k = 0; k + 1 < n; ++k) {
+      ld pn = ((x[i] - d[k]) * p - (k > 0 ? std::sqrt(e2[k]) * pm1 : 0)) / std::sqrt(e2[k + 1]);
+      pm1 = p;
+      p = pn;
+      sum += p * p;
+    }
+    w[i] = 1.0L / sum;
+  }
+}
+
+// Collapsed rule on the reference tetrahedron, n points per direction; barycentric
+// coordinates lam[q][4] and weights (sum = 4/3).
+void tet_rule(int n, std::vector<std::array<ld, 4>>& lam, std::vector<ld>& w) {
+  std::vector<ld> xa, wa, xb, wb, xc, wc;
+  gauss_jacobi(n, 0, 0, xa, wa);
+  gauss_jacobi(n, 1, 0, xb, wb);
+  gauss_jacobi(n, 2, 0, xc, wc);
+  lam.clear();
+  w.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        ld A = xa[i], B = xb[j], C = xc[k];
+        ld r = (1 + A) * (1 - B) * (1 - C) / 4 - 1;
+        ld s = (1 + B) * (1 - C) / 2 - 1;
+        ld t = C;
+        lam.push_back({-(1 + r + s + t) / 2, (1 + r) / 2, (1 + s) / 2, (1 + t) / 2});
+        w.push_back(wa[i] * wb[j] * wc[k] / 8);
+      }
+}
+
+ld bernstein(int n, const std::array<int, 4>& al, const std::array<ld, 4>& lam) {
+  ld v = factl(n);
+  for (int j = 0; j < 4; ++j) v = v / factl(al[j]) * std::pow(lam[j], (ld)al[j]);
+  return v;
+}
+
+// Dense closed-form Bernstein mass matrix of degree n on the volume-4/3 tetrahedron:
+// B_a B_b = C(a+b, a)/C(2n, n) B^{2n}_{a+b} and each degree-m Bernstein polynomial
+// integrates to (4/3)/C(m+3, 3).
+std::vector<ld> bernstein_mass(int n) {
+  auto A = mi3_list(n);
+  int np = (int)A.size();
+  std::vector<ld> Mm((size_t)np * np);
+  ld base = (4.0L / 3.0L) / (binoml(2 * n, n) * binoml(2 * n + 3, 3));
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      ld c = 1;
+      for (int q = 0; q < 4; ++q) c *= binoml(A[i][q] + A[j][q], A[i][q]);
+      Mm[(size_t)i * np + j] = c * base;
+    }
+  return Mm;
+}
+
+// Projection onto degree d from samples at the collapsed rule with d+3 points per
+// direction: P = M_d^{-1} B^T W ([dimp(d)][nq], long-double Cholesky), plus B itself.
+struct Projector {
+  int degree = -1;
+  int nq = 0;
+  std::vector<double> P;     // [dimp][nq]
+  std::vector<double> B;     // [nq][dimp] Bernstein values at the points
+  std::vector<std::array<ld, 4>> lam;
+};
+
+void build_projector(int d, Projector& pr) {
+  int n = d + 3;
+  std::vector<ld> w;
+  tet_rule(n, pr.lam, w);
+  int nq = (int)w.size();
+  auto A = mi3_list(d);
+  int np = (int)A.size();
+  std::vector<ld> Bq((size_t)nq * np);
+  for (int q = 0; q < nq; ++q)
+    for (int i = 0; i < np; ++i) Bq[(size_t)q * np + i] = bernstein(d, A[i], pr.lam[q]);
+  std::vector<ld> L = bernstein_mass(d);
+  // Cholesky L L^T = M
+  for (int j = 0; j < np; ++j) {
+    ld s = L[(size_t)j * np + j];
+    for (int k = 0; k < j; ++k) s -= L[(size_t)j * np + k] * L[(size_t)j * np + k];
+    ld djj = std::sqrt(s);
+    L[(size_t)j * np + j] = djj;
+    for (int i = j + 1; i < np; ++i) {
+      ld t = L[(size_t)i * np + j];
+      for (int k = 0; k < j; ++k) t -= L[(size_t)i * np + k] * L[(size_t)j * np + k];
+      L[(size_t)i * np + j] = t / djj;
+    }
+  }
+  pr.P.assign((size_t)np * nq, 0);
+  std::vector<ld> col(np);
+  for (int q = 0; q < nq; ++q) {
+    for (int i = 0; i < np; ++i) col[i] = Bq[(size_t)q * np + i] * w[q];
+    for (int i = 0; i < np; ++i) {  // forward
+      ld t = col[i];
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * np + k] * col[k];
+      col[i] = t / L[(size_t)i * np + i];
+    }
+    for (int i = np - 1; i >= 0; --i) {  // backward
+      ld t = col[i];
+      for (int k = i + 1; k < np; ++k) t -= L[(size_t)k * np + i] * col[k];
+      col[i] = t / L[(size_t)i * np + i];
+    }
+    for (int i = 0; i < np; ++i) pr.P[(size_t)i * nq + q] = (double)col[i];
+  }
+  pr.B.assign((size_t)nq * np, 0);
+  for (size_t i = 0; i < Bq.size(); ++i) pr.B[i] = (double)Bq[i];
+  pr.degree = d;
+  pr.nq = nq;
+}
+
+// ------------------------------------------------------------------------ tables
+struct HostTables {
+  TableOffsets off{};
+  std::vector<uint16_t> tab;
+  std::vector<double> mulw;  // [dimp(N+M)][dimp(M)]
+  double cj[kMaxN + 1] = {0};
+  double ell[kMaxN + 1] = {0};
+};
+
+void build_tables(int N, int M, HostTables& T) {
+  std::vector<uint16_t>& t = T.tab;
+  TableOffsets& o = T.off;
+  auto put4 = [&](int a, int b, int c, int d) {
+    t.push_back((uint16_t)a); t.push_back((uint16_t)b); t.push_back((uint16_t)c); t.push_back((uint16_t)d);
+  };
+  auto u16 = [](int v) { return v < 0 ? (int)kNone : v; };
+  for (int n = 0; n <= N + M; ++n) {
+    o.mi3[n] = (int)t.size();
+    for (auto& a : mi3_list(n)) put4(a[0], a[1], a[2], a[3]);
+  }
+  for (int n = 1; n <= N + M; ++n) {  // elevation n-1 -> n: gamma - e_k
+    o.el3[n] = (int)t.size();
+    for (auto& g : mi3_list(n)) {
+      int ix[4];
+      for (int k = 0; k < 4; ++k) {
+        auto h = g;
+        h[k] -= 1;
+        ix[k] = (g[k] > 0) ? idx3(n - 1, h) : -1;
+      }
+      put4(u16(ix[0]), u16(ix[1]), u16(ix[2]), u16(ix[3]));
+    }
+  }
+  for (int n = 1; n <= N + M; ++n) {  // reduction n -> n-1: alpha + e_k at degree n
+    o.red3[n] = (int)t.size();
+    for (auto& a : mi3_list(n - 1)) {
+      int ix[4];
+      for (int k = 0; k < 4; ++k) {
+        auto h = a;
+        h[k] += 1;
+        ix[k] = idx3(n, h);
+      }
+      put4(ix[0], ix[1], ix[2], ix[3]);
+    }
+  }
+  for (int n = 0; n <= N; ++n) {
+    o.mi2[n] = (int)t.size();
+    for (auto& b : mi2_list(n)) put4(b[0], b[1], b[2], 0);
+  }
+  o.el2 = (int)t.size();
+  for (auto& g : mi2_list(N)) {
+    int ix[3];
+    for (int k = 0; k < 3; ++k) {
+      auto h = g;
+      h[k] -= 1;
+      ix[k] = (g[k] > 0) ? idx2(N - 1, h) : -1;
+    }
+    put4(u16(ix[0]), u16(ix[1]), u16(ix[2]), kNone);
+  }
+  for (int n = 1; n <= N; ++n) {
+    o.red2[n] = (int)t.size();
+    for (auto& b : mi2_list(n - 1)) {
+      int ix[3];
+      for (int k = 0; k < 3; ++k) {
+        auto h = b;
+        h[k] += 1;
+        ix[k] = idx2(n, h);
+      }
+      put4(ix[0], ix[1], ix[2], kNone);
+    }
+  }
+  // face f is opposite local vertex f; its vertices in increasing local order u0<u1<u2
+  auto face_verts = [](int f, int u[3]) {
+    int m = 0;
+    for (int v = 0; v < 4; ++v)
+      if (v != f) u[m++] = v;
+  };
+  o.fidx = (int)t.size();
+  auto F2 = mi2_list(N);
+  for (int f = 0; f < 4; ++f) {
+    int u[3];
+    face_verts(f, u);
+    for (auto& b : F2) {
+      std::array<int, 4> a = {0, 0, 0, 0};
+      for (int m = 0; m < 3; ++m) a[u[m]] = b[m];
+      t.push_back((uint16_t)idx3(N, a));
+    }
+  }
+  while (t.size() % 4) t.push_back(0);
+  o.liftpos = (int)t.size();
+  int choff[kMaxN + 2];
+  choff[0] = 0;
+  for (int i = 0; i <= N; ++i) choff[i + 1] = choff[i] + dim2(N - i);
+  for (int f = 0; f < 4; ++f) {
+    int u[3];
+    face_verts(f, u);
+    for (auto& a : mi3_list(N)) {
+      int i = a[f];
+      std::array<int, 3> b = {a[u[0]], a[u[1]], a[u[2]]};
+      t.push_back((uint16_t)(choff[i] + idx2(N - i, b)));
+    }
+  }
+  while (t.size() % 4) t.push_back(0);
+  o.mulidx = (int)t.size();
+  auto H = mi3_list(N + M);
+  auto Bm = mi3_list(M);
+  T.mulw.assign(H.size() * Bm.size(), 0.0);
+  ld inv = 1.0L / binoml(N + M, N);
+  for (size_t g = 0; g < H.size(); ++g)
+    for (size_t b = 0; b < Bm.size(); ++b) {
+      std::array<int, 4> d;
+      bool ok = true;
+      ld wgt = inv;
+      for (int k = 0; k < 4; ++k) {
+        d[k] = H[g][k] - Bm[b][k];
+        if (d[k] < 0) ok = false;
+        else wgt *= binoml(H[g][k], Bm[b][k]);
+      }
+      t.push_back(ok ? (uint16_t)idx3(N, d) : kNone);
+      T.mulw[g * Bm.size() + b] = ok ? (double)wgt : 0.0;
+    }
+  while (t.size() % 4) t.push_back(0);
+  o.total = (int)t.size();
+  ld c[kMaxN + 1];
+  projection_cj(N, M, c);
+  for (int j = 0; j <= N; ++j) T.cj[j] = (double)c[j];
+  for (int i = 0; i <= N; ++i) T.ell[i] = (double)((i % 2 ? -1.0L : 1.0L) * binoml(N, i) / (i + 1));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ context
+struct bbwadg_ctx {
+  int N = 0, M = 0, dtype = 0, mode = 0, bc = 0;
+  double tau_p = 1, tau_u = 1;
+  int64_t K = 0, Nv = 0;
+  int Np = 0, Nfp = 0, Mp = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> etov;     // sorted per element
+  std::vector<double> J;         // [K]
+  std::vector<double> G;         // [K][9]
+  std::vector<double> nrm;       // [K][4][3]
+  std::vector<double> fscale;    // [K][4]
+  std::vector<int32_t> conn;     // [K][4]
+  std::vector<double> c2;        // [K][Mp]
+  bool c2_set = false, c2_dirty = false;
+  HostTables tables;
+  Projector proj[kMaxN + 1];
+  // device
+  int device = -1;
+  size_t rsz = 8;
+  void* d_geo = nullptr;
+  void* d_conn = nullptr;
+  void* d_c2 = nullptr;
+  void* d_tab = nullptr;
+  void* d_mulw = nullptr;
+  void* d_q2 = nullptr;
+  void* d_J = nullptr;
+  void* d_mass = nullptr;
+  void* d_partial = nullptr;
+  int nred_blocks = 0;
+};
+
+namespace {
+
+// Split [a, b) over hardware threads (setup-time host loops only).
+template <typename F>
+void parallel_for(int64_t a, int64_t b, F&& fn) {
+  int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+  if (b - a < 256) nt = 1;
+  if (nt == 1) { fn(a, b); return; }
+  std::vector<std::thread> th;
+  int64_t chunk = (b - a + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    int64_t lo = a + t * chunk, hi = std::min(b, lo + chunk);
+    if (lo < hi) th.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
+  auto* c = const_cast<bbwadg_ctx*>(ctx);
+  if (c->proj[d].degree != d) build_projector(d, c->proj[d]);
+  return c->proj[d];
+}
+
+void free_device(bbwadg_ctx* c) {
+  void** ptrs[] = {&c->d_geo, &c->d_conn, &c->d_c2, &c->d_tab, &c->d_mulw, &c->d_q2,
+                   &c->d_J, &c->d_mass, &c->d_partial};
+  for (void** p : ptrs) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+}
+
+template <typename real>
+std::vector<real> convert(const std::vector<double>& v) {
+  return std::vector<real>(v.begin(), v.end());
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  return e == hipSuccess ? 0 : fail(BBWADG_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+}
+
+int dmalloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+  return e == hipSuccess ? 0 : fail(BBWADG_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+}
+
+// c^2_M must be finite and positive at the points of the degree-M projection rule.
+int check_c2(const bbwadg_ctx* ctx, const double* coef, int64_t k0, int64_t k1) {
+  const Projector& pr = get_projector(ctx, ctx->M);
+  int mp = ctx->Mp;
+  for (int64_t k = k0; k < k1; ++k) {
+    const double* c = coef + (k - k0) * mp;
+    for (int i = 0; i < mp; ++i)
+      if (!std::isfinite(c[i])) return fail(BBWADG_EC2, "c^2 coefficient of element %lld not finite", (long long)k);
+    for (int q = 0; q < pr.nq; ++q) {
+      double v = 0;
+      for (int i = 0; i < mp; ++i) v += pr.B[(size_t)q * mp + i] * c[i];
+      if (!(v > 0)) return fail(BBWADG_EC2, "c^2_M <= 0 in element %lld", (long long)k);
+    }
+  }
+  return 0;
+}
+
+int sync_c2(bbwadg_ctx* ctx, hipStream_t s) {
+  if (!ctx->c2_set) return fail(BBWADG_EC2, "c^2 not set (call bbwadg_project_c2 or bbwadg_set_c2)");
+  if (!ctx->c2_dirty) return 0;
+  hipError_t e;
+  if (ctx->dtype == BBWADG_F64) {
+    e = hipMemcpyAsync(ctx->d_c2, ctx->c2.data(), ctx->c2.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  } else {
+    std::vector<float> f = convert<float>(ctx->c2);
+    e = hipMemcpyAsync(ctx->d_c2, f.data(), f.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // f is a local buffer
+  }
+  if (e != hipSuccess) return fail(BBWADG_EHIP, "c^2 upload: %s", hipGetErrorString(e));
+  ctx->c2_dirty = false;
+  return 0;
+}
+
+template <typename real>
+StageArgs<real> make_args(const bbwadg_ctx* c) {
+  StageArgs<real> a{};
+  a.geo = (const real*)c->d_geo;
+  a.conn = (const int32_t*)c->d_conn;
+  a.c2 = (const real*)c->d_c2;
+  a.tab = (const uint16_t*)c->d_tab;
+  a.mulw = (const real*)c->d_mulw;
+  a.off = c->tables.off;
+  a.K = c->K;
+  a.tau_p = (real)c->tau_p;
+  a.tau_u = (real)c->tau_u;
+  a.bc = c->bc;
+  for (int j = 0; j <= kMaxN; ++j) {
+    a.cj[j] = (real)c->tables.cj[j];
+    a.ell[j] = (real)c->tables.ell[j];
+  }
+  return a;
+}
+
+const double kRkA[5] = {0.0,
+                        -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
+                        5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0,
+                        3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, double ra, double rb,
+           double dt, hipStream_t s) {
+  int e;
+  if (c->dtype == BBWADG_F64) {
+    StageArgs<double> a = make_args<double>(c);
+    a.qin = (const double*)qin;
+    a.qout = (double*)qout;
+    a.res = (double*)res;
+    a.rk_a = ra;
+    a.rk_b = rb;
+    a.dt = dt;
+    e = launch_stage_f64(c->N, c->M, update, a, s);
+  } else {
+    StageArgs<float> a = make_args<float>(c);
+    a.qin = (const float*)qin;
+    a.qout = (float*)qout;
+    a.res = (float*)res;
+    a.rk_a = (float)ra;
+    a.rk_b = (float)rb;
+    a.dt = (float)dt;
+    e = launch_stage_f32(c->N, c->M, update, a, s);
+  }
+  if (e != 0) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
+}
+
+int require_device(const bbwadg_ctx* c) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (c->mode != BBWADG_DEVICE) return fail(BBWADG_EINVAL, "host-only context");
+  return 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* bbwadg_last_error(void) { return g_err.c_str(); }
+const char* bbwadg_version(void) { return "bbwadg-mi355x 0.1"; }
+
+int bbwadg_projection_coefficients(int32_t N, int32_t M, double* cj_out) {
+  if (N < 1 || N > kMaxN || M < -1 || M > 9 || !cj_out) return fail(BBWADG_EINVAL, "bad N/M");
+  ld c[kMaxN + 1];
+  projection_cj(N, M, c);
+  for (int j = 0; j <= N; ++j) cj_out[j] = (double)c[j];
+  return 0;
+}
+
+int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx** out) {
+  g_err.clear();
+  if (!mesh || !opts || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int N = opts->N, M = opts->M;
+  if (N < 1 || N > kMaxN) return fail(BBWADG_EINVAL, "N=%d outside [1,%d]", N, kMaxN);
+  if (M < 0 || M > std::min(N, kMaxM)) return fail(BBWADG_EINVAL, "M=%d outside [0,min(N,%d)]", M, kMaxM);
+  if (opts->dtype != BBWADG_F64 && opts->dtype != BBWADG_F32) return fail(BBWADG_EINVAL, "bad dtype");
+  if (opts->mode != BBWADG_DEVICE && opts->mode != BBWADG_HOST_ONLY) return fail(BBWADG_EINVAL, "bad mode");
+  if (!(opts->tau_p >= 0) || !(opts->tau_u >= 0) || !std::isfinite(opts->tau_p) || !std::isfinite(opts->tau_u))
+    return fail(BBWADG_EINVAL, "tau must be finite and >= 0");
+  if (mesh->bc != BBWADG_BC_P0 && mesh->bc != BBWADG_BC_RIGID) return fail(BBWADG_EINVAL, "bad bc");
+  if (mesh->num_elements < 1 || mesh->num_vertices < 4 || !mesh->xyz || !mesh->etov)
+    return fail(BBWADG_EINVAL, "empty mesh or NULL arrays");
+  if (mesh->num_elements > (int64_t)1 << 28) return fail(BBWADG_EINVAL, "too many elements");
+  const int64_t K = mesh->num_elements, Nv = mesh->num_vertices;
+
+  bbwadg_ctx* c = new (std::nothrow) bbwadg_ctx();
+  if (!c) return fail(BBWADG_ENOMEM, "context");
+  c->N = N; c->M = M; c->dtype = opts->dtype; c->mode = opts->mode; c->bc = mesh->bc;
+  c->tau_p = opts->tau_p; c->tau_u = opts->tau_u;
+  c->K = K; c->Nv = Nv;
+  c->Np = dimp(N); c->Nfp = dim2(N); c->Mp = dimp(M);
+  c->rsz = (c->dtype == BBWADG_F64) ? 8 : 4;
+  c->xyz.assign(mesh->xyz, mesh->xyz + 3 * Nv);
+  c->etov.resize(4 * K);
+  for (int64_t k = 0; k < K; ++k) {
+    int32_t v[4];
+    for (int j = 0; j < 4; ++j) {
+      v[j] = mesh->etov[4 * k + j];
+      if (v[j] < 0 || v[j] >= Nv) { delete c; return fail(BBWADG_EINVAL, "vertex id out of range in element %lld", (long long)k); }
+    }
+    std::sort(v, v + 4);
+    if (v[0] == v[1] || v[1] == v[2] || v[2] == v[3]) { delete c; return fail(BBWADG_EMESH, "repeated vertex in element %lld", (long long)k); }
+    for (int j = 0; j < 4; ++j) c->etov[4 * k + j] = v[j];
+  }
+  // geometry
+  c->J.resize(K); c->G.resize(9 * K); c->nrm.resize(12 * K); c->fscale.resize(4 * K);
+  for (int64_t k = 0; k < K; ++k) {
+    double V[4][3];
+    for (int j = 0; j < 4; ++j)
+      for (int d = 0; d < 3; ++d) V[j][d] = c->xyz[3 * (size_t)c->etov[4 * k + j] + d];
+    double A[3][3];  // A[i][j] = d x_i / d r_j
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[i][j] = 0.5 * (V[j + 1][i] - V[0][i]);
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    double h = 0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        double d2 = 0;
+        for (int d = 0; d < 3; ++d) d2 += (V[a][d] - V[b][d]) * (V[a][d] - V[b][d]);
+        h = std::max(h, std::sqrt(d2));
+      }
+    if (!(std::fabs(det) > 1e-14 * h * h * h)) { delete c; return fail(BBWADG_EMESH, "degenerate element %lld", (long long)k); }
+    double inv[3][3];  // inverse of A: inv[j][i] = d r_j / d x_i
+    inv[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+    inv[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+    inv[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+    inv[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+    inv[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+    inv[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+    inv[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+    inv[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+    inv[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+    double J = std::fabs(det);
+    c->J[k] = J;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) c->G[9 * k + 3 * i + j] = inv[j][i];
+    for (int f = 0; f < 4; ++f) {
+      int u[3], m = 0;
+      for (int v = 0; v < 4; ++v)
+        if (v != f) u[m++] = v;
+      double e1[3], e2[3], cr[3];
+      for (int d = 0; d < 3; ++d) { e1[d] = V[u[1]][d] - V[u[0]][d]; e2[d] = V[u[2]][d] - V[u[0]][d]; }
+      cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      double dotv = 0;
+      for (int d = 0; d < 3; ++d) dotv += cr[d] * (V[u[0]][d] - V[f][d]);
+      double sg = dotv > 0 ? 1.0 : -1.0;
+      for (int d = 0; d < 3; ++d) c->nrm[12 * k + 3 * f + d] = sg * cr[d] / len;
+      double area = 0.5 * len;
+      c->fscale[4 * k + f] = (area / 2.0) / J;
+    }
+  }
+  // connectivity: match faces by their sorted global vertex triple
+  {
+    struct Key { int32_t a, b, c; bool operator==(const Key& o) const { return a == o.a && b == o.b && c == o.c; } };
+    struct H { size_t operator()(const Key& k) const { return ((size_t)k.a * 0x9E3779B97F4A7C15ull) ^ ((size_t)k.b * 0xC2B2AE3D27D4EB4Full) ^ ((size_t)k.c * 0x165667B19E3779F9ull); } };
+    std::unordered_map<Key, int64_t, H> faces;
+    faces.reserve((size_t)(2.5 * K) + 16);
+    c->conn.assign(4 * K, -1);
+    for (int64_t k = 0; k < K; ++k)
+      for (int f = 0; f < 4; ++f) {
+        int32_t u[3], m = 0;
+        for (int v = 0; v < 4; ++v)
+          if (v != f) u[m++] = c->etov[4 * k + v];
+        Key key{u[0], u[1], u[2]};  // already ascending
+        auto it = faces.find(key);
+        if (it == faces.end()) {
+          faces.emplace(key, 4 * k + f);
+        } else {
+          int64_t other = it->second;
+          if (other < 0) { delete c; return fail(BBWADG_EMESH, "face shared by more than two elements (element %lld)", (long long)k); }
+          c->conn[4 * k + f] = (int32_t)other;
+          c->conn[other] = (int32_t)(4 * k + f);
+          it->second = -1;
+        }
+      }
+  }
+  build_tables(N, M, c->tables);
+  if (c->mode == BBWADG_HOST_ONLY) { *out = c; return 0; }
+
+  // device buffers
+  int rc = 0;
+  hipError_t he = hipGetDevice(&c->device);
+  if (he != hipSuccess) { delete c; return fail(BBWADG_EHIP, "hipGetDevice: %s", hipGetErrorString(he)); }
+  std::vector<double> geo((size_t)K * kGeoStride);
+  for (int64_t k = 0; k < K; ++k) {
+    double* g = &geo[(size_t)k * kGeoStride];
+    for (int i = 0; i < 9; ++i) g[i] = c->G[9 * k + i];
+    for (int f = 0; f < 4; ++f) {
+      g[9 + 4 * f] = c->fscale[4 * k + f];
+      for (int d = 0; d < 3; ++d) g[9 + 4 * f + 1 + d] = c->nrm[12 * k + 3 * f + d];
+    }
+  }
+  size_t rs = c->rsz;
+  const size_t qbytes = (size_t)4 * K * c->Np * rs;
+  c->nred_blocks = 1024;
+  if ((rc = dmalloc(&c->d_geo, geo.size() * rs)) || (rc = dmalloc(&c->d_conn, c->conn.size() * 4)) ||
+      (rc = dmalloc(&c->d_c2, (size_t)K * c->Mp * rs)) || (rc = dmalloc(&c->d_tab, c->tables.tab.size() * 2)) ||
+      (rc = dmalloc(&c->d_mulw, c->tables.mulw.size() * rs)) || (rc = dmalloc(&c->d_q2, qbytes)) ||
+      (rc = dmalloc(&c->d_J, (size_t)K * 8)) || (rc = dmalloc(&c->d_mass, (size_t)c->Np * c->Np * 8)) ||
+      (rc = dmalloc(&c->d_partial, (size_t)c->nred_blocks * 4 * 8))) {
+    free_device(c);
+    delete c;
+    return rc;
+  }
+  std::vector<ld> mass = bernstein_mass(N);
+  std::vector<double> massd(mass.begin(), mass.end());
+  if (rs == 8) {
+    rc = upload(c->d_geo, geo.data(), geo.size() * 8);
+    if (!rc) rc = upload(c->d_mulw, c->tables.mulw.data(), c->tables.mulw.size() * 8);
+  } else {
+    std::vector<float> gf = convert<float>(geo), mf = convert<float>(c->tables.mulw);
+    rc = upload(c->d_geo, gf.data(), gf.size() * 4);
+    if (!rc) rc = upload(c->d_mulw, mf.data(), mf.size() * 4);
+  }
+  if (!rc) rc = upload(c->d_conn, c->conn.data(), c->conn.size() * 4);
+  if (!rc) rc = upload(c->d_tab, c->tables.tab.data(), c->tables.tab.size() * 2);
+  if (!rc) rc = upload(c->d_J, c->J.data(), (size_t)K * 8);
+  if (!rc) rc = upload(c->d_mass, massd.data(), massd.size() * 8);
+  if (rc) { free_device(c); delete c; return rc; }
+  *out = c;
+  return 0;
+}
+
+int bbwadg_destroy(bbwadg_ctx* ctx) {
+  if (!ctx) return 0;
+  if (ctx->mode == BBWADG_DEVICE) {
+    (void)hipDeviceSynchronize();
+    free_device(ctx);
+  }
+  delete ctx;
+  return 0;
+}
+
+int bbwadg_sizes(const bbwadg_ctx* c, int32_t* Np, int32_t* Nfp, int32_t* Mp, int64_t* K) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (Np) *Np = c->Np;
+  if (Nfp) *Nfp = c->Nfp;
+  if (Mp) *Mp = c->Mp;
+  if (K) *K = c->K;
+  return 0;
+}
+
+int bbwadg_element_vertices(const bbwadg_ctx* c, int32_t* etov_out) {
+  if (!c || !etov_out) return fail(BBWADG_EINVAL, "NULL argument");
+  std::memcpy(etov_out, c->etov.data(), c->etov.size() * 4);
+  return 0;
+}
+
+int bbwadg_geometry(const bbwadg_ctx* c, double* J, double* G, double* normal, double* Fscale, int32_t* nbr) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (J) std::memcpy(J, c->J.data(), c->J.size() * 8);
+  if (G) std::memcpy(G, c->G.data(), c->G.size() * 8);
+  if (normal) std::memcpy(normal, c->nrm.data(), c->nrm.size() * 8);
+  if (Fscale) std::memcpy(Fscale, c->fscale.data(), c->fscale.size() * 8);
+  if (nbr) std::memcpy(nbr, c->conn.data(), c->conn.size() * 4);
+  return 0;
+}
+
+int bbwadg_projection_npoints(const bbwadg_ctx* c, int32_t degree, int64_t* nq) {
+  if (!c || !nq) return fail(BBWADG_EINVAL, "NULL argument");
+  if (degree < 0 || degree > kMaxN) return fail(BBWADG_EINVAL, "degree outside [0,%d]", kMaxN);
+  *nq = (int64_t)(degree + 3) * (degree + 3) * (degree + 3);
+  return 0;
+}
+
+int bbwadg_projection_points(const bbwadg_ctx* c, int32_t degree, int64_t k0, int64_t k1, double* xyz_out) {
+  if (!c || !xyz_out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (degree < 0 || degree > kMaxN) return fail(BBWADG_EINVAL, "degree outside [0,%d]", kMaxN);
+  if (k0 < 0 || k1 > c->K || k0 > k1) return fail(BBWADG_EINVAL, "bad element range");
+  const Projector& pr = get_projector(c, degree);
+  for (int64_t k = k0; k < k1; ++k) {
+    const int32_t* v = &c->etov[4 * k];
+    for (int q = 0; q < pr.nq; ++q)
+      for (int d = 0; d < 3; ++d) {
+        ld x = 0;
+        for (int j = 0; j < 4; ++j) x += pr.lam[q][j] * (ld)c->xyz[3 * (size_t)v[j] + d];
+        xyz_out[((size_t)(k - k0) * pr.nq + q) * 3 + d] = (double)x;
+      }
+  }
+  return 0;
+}
+
+int bbwadg_project_samples(const bbwadg_ctx* c, int32_t degree, int64_t k0, int64_t k1, const double* samples,
+                           double* coef_out) {
+  if (!c || !samples || !coef_out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (degree < 0 || degree > kMaxN) return fail(BBWADG_EINVAL, "degree outside [0,%d]", kMaxN);
+  if (k0 < 0 || k1 > c->K || k0 > k1) return fail(BBWADG_EINVAL, "bad element range");
+  const Projector& pr = get_projector(c, degree);
+  const int np = dimp(degree), nq = pr.nq;
+  auto work = [&](int64_t a, int64_t b) {
+    for (int64_t k = a; k < b; ++k) {
+      const double* s = samples + (size_t)(k - k0) * nq;
+      double* o = coef_out + (size_t)(k - k0) * np;
+      for (int i = 0; i < np; ++i) {
+        const double* P = &pr.P[(size_t)i * nq];
+        double acc = 0;
+        for (int q = 0; q < nq; ++q) acc += P[q] * s[q];
+        o[i] = acc;
+      }
+    }
+  };
+  parallel_for(k0, k1, work);
+  return 0;
+}
+
+int bbwadg_set_c2(bbwadg_ctx* c, const double* coef) {
+  if (!c || !coef) return fail(BBWADG_EINVAL, "NULL argument");
+  int rc = check_c2(c, coef, 0, c->K);
+  if (rc) return rc;
+  c->c2.assign(coef, coef + (size_t)c->K * c->Mp);
+  c->c2_set = true;
+  c->c2_dirty = true;
+  return 0;
+}
+
+int bbwadg_get_c2(const bbwadg_ctx* c, double* coef) {
+  if (!c || !coef) return fail(BBWADG_EINVAL, "NULL argument");
+  if (!c->c2_set) return fail(BBWADG_EC2, "c^2 not set");
+  std::memcpy(coef, c->c2.data(), c->c2.size() * 8);
+  return 0;
+}
+
+int bbwadg_project_c2(bbwadg_ctx* c, double (*fn)(double, double, double, void*), void* user, void* c2_out,
+                      void* stream) {
+  if (!c || !fn) return fail(BBWADG_EINVAL, "NULL argument");
+  if (c2_out && c->mode != BBWADG_DEVICE) return fail(BBWADG_EINVAL, "c2_out needs a device context");
+  const Projector& pr = get_projector(c, c->M);
+  const int64_t K = c->K;
+  std::vector<double> coef((size_t)K * c->Mp);
+  const int64_t chunk = 4096;
+  std::vector<double> xyz, smp;
+  for (int64_t k0 = 0; k0 < K; k0 += chunk) {
+    int64_t k1 = std::min(K, k0 + chunk);
+    xyz.resize((size_t)(k1 - k0) * pr.nq * 3);
+    smp.resize((size_t)(k1 - k0) * pr.nq);
+    int rc = bbwadg_projection_points(c, c->M, k0, k1, xyz.data());
+    if (rc) return rc;
+    for (size_t i = 0; i < smp.size(); ++i) smp[i] = fn(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], user);
+    rc = bbwadg_project_samples(c, c->M, k0, k1, smp.data(), &coef[(size_t)k0 * c->Mp]);
+    if (rc) return rc;
+  }
+  int rc = bbwadg_set_c2(c, coef.data());
+  if (rc) return rc;
+  if (c2_out) {
+    hipStream_t s = (hipStream_t)stream;
+    rc = sync_c2(c, s);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(c2_out, c->d_c2, (size_t)K * c->Mp * c->rsz, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(BBWADG_EHIP, "c2 copy: %s", hipGetErrorString(e));
+  }
+  return 0;
+}
+
+int bbwadg_rhs(bbwadg_ctx* c, const void* q, void* rhs, double t, void* stream) {
+  (void)t;
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !rhs) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (q == rhs) return fail(BBWADG_EINVAL, "q and rhs must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s))) return rc;
+  return launch(c, false, q, rhs, nullptr, 0.0, 0.0, 0.0, s);
+}
+
+int bbwadg_step(bbwadg_ctx* c, void* q, void* res, double t0, double dt, int32_t nsteps, void* stream) {
+  (void)t0;
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !res) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (q == res) return fail(BBWADG_EINVAL, "q and res must not overlap");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(BBWADG_EINVAL, "bad nsteps or dt");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s))) return rc;
+  void* cur = q;
+  void* nxt = c->d_q2;
+  for (int32_t n = 0; n < nsteps; ++n)
+    for (int st = 0; st < 5; ++st) {
+      if ((rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, s))) return rc;
+      std::swap(cur, nxt);
+    }
+  if (cur != q) {
+    hipError_t e = hipMemcpyAsync(q, cur, (size_t)4 * c->K * c->Np * c->rsz, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(BBWADG_EHIP, "state copy: %s", hipGetErrorString(e));
+  }
+  return 0;
+}
+
+int bbwadg_suggest_dt(const bbwadg_ctx* c, double cfl, double* dt) {
+  if (!c || !dt) return fail(BBWADG_EINVAL, "NULL argument");
+  if (!(cfl > 0)) return fail(BBWADG_EINVAL, "cfl must be > 0");
+  if (!c->c2_set) return fail(BBWADG_EC2, "c^2 not set");
+  double c2max = 0, fmax = 0;
+  for (double v : c->c2) c2max = std::max(c2max, v);
+  for (double v : c->fscale) fmax = std::max(fmax, v);
+  double CN = (c->N + 1.0) * (c->N + 3.0) / 3.0;
+  *dt = cfl / (std::sqrt(c2max) * CN * fmax);
+  return 0;
+}
+
+int bbwadg_l2norm2(bbwadg_ctx* c, const void* q, double out[4], void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  int e = launch_l2norm(c->N, c->dtype, q, c->K, (const double*)c->d_J, (const double*)c->d_mass,
+                        (double*)c->d_partial, c->nred_blocks, s);
+  if (e) return fail(BBWADG_EHIP, "l2norm launch: %s", hipGetErrorString((hipError_t)e));
+  std::vector<double> part((size_t)c->nred_blocks * 4);
+  hipError_t he = hipMemcpyAsync(part.data(), c->d_partial, part.size() * 8, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return fail(BBWADG_EHIP, "l2norm copy: %s", hipGetErrorString(he));
+  for (int f = 0; f < 4; ++f) {
+    double acc = 0;
+    for (int b = 0; b < c->nred_blocks; ++b) acc += part[(size_t)b * 4 + f];
+    out[f] = acc;
+  }
+  return 0;
+}
+
+}  // extern "C"

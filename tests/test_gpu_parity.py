@@ -1,0 +1,268 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Both sides take the same seeded inputs (workloads module): mesh, Bernstein state, c^2
+Bernstein coefficients or c^2 function, dt. Results are compared as functions at the
+oracle's quadrature points, per field, by relative L^2 norm over the mesh.
+
+Tolerances: FP64 1e-11 (relative L^2 per field). FP32: 1e-5 per field for N <= 7; for
+N = 8, 9 the roundoff amplification sum |c_j| of the telescoped projection reaches 259
+and 524 (14.5 at N = 7, M = 1), so single-precision results are held to 2e-4 there.
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from workloads import (c2_gaussian_bumps, c2_sinusoid, exact_cos_mode, exact_sin_mode, ic_cos_product,
+                       ic_gaussian_pulse, kuhn_cube_mesh, random_c2_coefficients, random_state)
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-11
+
+
+def fp32_tol(N):
+    return 1e-5 if N <= 7 else 2e-4
+
+
+@pytest.fixture(scope="module")
+def bb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1808_08645_amd as bb
+    bb.load_library()
+    return bb
+
+
+def dimp(n):
+    return (n + 1) * (n + 2) * (n + 3) // 6
+
+
+def _compare(o, q_gpu, Q_oracle):
+    """Per-field relative L^2 of the device Bernstein state vs oracle modal state."""
+    a = o.bernstein_values_at_quad(q_gpu.double().cpu().numpy())
+    b = o.values_at_quad(Q_oracle)
+    return o.rel_l2(a, b)
+
+
+RHS_CASES = [(1, 0), (1, 1), (2, 1), (2, 2), (3, 0), (3, 1), (3, 2), (4, 2), (5, 2), (5, 1), (6, 3), (7, 3),
+             (8, 4), (9, 4)]
+
+
+@pytest.mark.parametrize("N,M", RHS_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rhs_parity_random_state(bb, N, M, dtype):
+    print(f"[rhs parity] N={N} M={M} {dtype}", flush=True)
+    xyz, etov = kuhn_cube_mesh(2)  # 48 tets: interior and boundary faces, every face orientation
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    q = random_state(11, s.K, s.Np)
+    c2 = random_c2_coefficients(12, s.K, s.Mp)
+    s.set_c2(c2)
+    out = s.rhs(s.to_device(q))
+    o = Oracle(xyz, etov, N, M)
+    o.set_c2_bernstein(c2)
+    err = _compare(o, out, o.rhs(o.from_bernstein(q)))
+    tol = FP64_TOL if dtype == "f64" else fp32_tol(N)
+    assert np.all(err < tol), err
+
+
+@pytest.mark.parametrize("bc", ["p0", "rigid"])
+@pytest.mark.parametrize("tau", [(1.0, 1.0), (0.0, 0.0), (0.3, 2.5)])
+def test_rhs_parity_boundary_and_penalty(bb, bc, tau):
+    print(f"[rhs bc/tau] {bc} {tau}", flush=True)
+    xyz, etov = kuhn_cube_mesh(3)
+    N, M = 4, 2
+    s = bb.Solver(xyz, etov, N, M, tau_p=tau[0], tau_u=tau[1], bc=bc)
+    q = random_state(21, s.K, s.Np)
+    c2 = random_c2_coefficients(22, s.K, s.Mp)
+    s.set_c2(c2)
+    out = s.rhs(s.to_device(q))
+    o = Oracle(xyz, etov, N, M, tau_p=tau[0], tau_u=tau[1], bc=bc)
+    o.set_c2_bernstein(c2)
+    err = _compare(o, out, o.rhs(o.from_bernstein(q)))
+    assert np.all(err < FP64_TOL), err
+
+
+@pytest.mark.parametrize("K_sel", [1, 5, 7, 13])
+@pytest.mark.parametrize("N,M", [(2, 1), (3, 1), (5, 2)])
+def test_rhs_small_and_ragged_meshes(bb, K_sel, N, M):
+    """A single tetrahedron (all faces on the boundary) and element counts that leave the
+    last wavefront partly empty."""
+    print(f"[rhs ragged] K={K_sel} N={N} M={M}", flush=True)
+    xyz, etov = kuhn_cube_mesh(2)
+    etov = etov[:K_sel]
+    s = bb.Solver(xyz, etov, N, M)
+    q = random_state(31, s.K, s.Np)
+    c2 = random_c2_coefficients(32, s.K, s.Mp)
+    s.set_c2(c2)
+    out = s.rhs(s.to_device(q))
+    o = Oracle(xyz, etov, N, M)
+    o.set_c2_bernstein(c2)
+    err = _compare(o, out, o.rhs(o.from_bernstein(q)))
+    assert np.all(err < FP64_TOL), err
+
+
+def _cube384(bb, dtype, bc="p0"):
+    xyz, etov = kuhn_cube_mesh(4)
+    N, M = 3, 1
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype, bc=bc)
+    o = Oracle(xyz, etov, N, M, bc=bc)
+    return xyz, etov, s, o
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_step_parity_cube384_config(bb, dtype):
+    """384 tets, N=3, M=1, c^2 = 1 + 0.5 sin sin sin projected to P^1, p = cos cos cos,
+    p = 0 walls, 10 LSRK4 steps at CFL 0.5: every step of the path including both
+    projections (each side with its own code)."""
+    import torch
+    print(f"[step cube384] {dtype}", flush=True)
+    _, _, s, o = _cube384(bb, dtype)
+    s.project_c2(c2_sinusoid)
+    o.set_c2_function(c2_sinusoid, project=True)
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    q0 = s.initial_state([ic_cos_product, zero, zero, zero])
+    Q0 = o.project_initial([ic_cos_product, zero, zero, zero])
+    dt = 0.5 * 0.25 / (np.sqrt(1.5) * 16.0)
+    q = s.to_device(q0)
+    res = torch.zeros_like(q)
+    s.step(q, res, dt, 10)
+    torch.cuda.synchronize()
+    Q, _ = o.step(Q0, np.zeros_like(Q0), dt, 10)
+    err = _compare(o, q, Q)
+    tol = FP64_TOL if dtype == "f64" else fp32_tol(3)
+    assert np.all(err < tol), err
+
+
+def test_step_in_chunks_equals_one_call(bb):
+    """Odd and even stage counts (ping-pong buffer with the final copy) agree exactly."""
+    import torch
+    _, _, s, _ = _cube384(bb, "f64")
+    s.set_c2(random_c2_coefficients(41, s.K, s.Mp))
+    q0 = s.to_device(random_state(42, s.K, s.Np))
+    qa, ra = q0.clone(), torch.zeros_like(q0)
+    s.step(qa, ra, 1e-3, 4)
+    qb, rb = q0.clone(), torch.zeros_like(q0)
+    for _ in range(4):
+        s.step(qb, rb, 1e-3, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, qb) and torch.equal(ra, rb)
+
+
+@pytest.mark.parametrize("bc,exact", [("p0", exact_sin_mode), ("rigid", exact_cos_mode)])
+def test_standing_wave_c1_against_exact_and_oracle(bb, bc, exact):
+    import torch
+    print(f"[standing wave] {bc}", flush=True)
+    xyz, etov = kuhn_cube_mesh(4)
+    N, M = 3, 1
+    s = bb.Solver(xyz, etov, N, M, bc=bc)
+    s.project_c2(lambda x, y, z: 1.0 + 0.0 * x)
+    fns = [lambda x, y, z, i=i: exact(x, y, z, 0.0)[i] for i in range(4)]
+    q = s.to_device(s.initial_state(fns))
+    res = torch.zeros_like(q)
+    T, n = 0.1, 20
+    s.step(q, res, T / n, n)
+    torch.cuda.synchronize()
+    o = Oracle(xyz, etov, N, M, bc=bc)
+    o.set_c2_bernstein(np.ones((s.K, s.Mp)))
+    X = o.mesh.map_points(o.rq, o.sq, o.tq)
+    ex = np.stack(exact(X[..., 0], X[..., 1], X[..., 2], T))
+    vals = o.bernstein_values_at_quad(q.cpu().numpy())
+    err = np.sqrt(o.l2_sq(vals - ex).sum() / o.l2_sq(ex).sum())
+    assert err < 5e-3, err  # h = 1/4, N = 3: O(h^4) discretisation error
+    Q, _ = o.step(o.project_initial(fns), np.zeros((4, s.K, s.Np)), T / n, n)
+    assert np.all(_compare(o, q, Q) < FP64_TOL)
+
+
+def test_l2norm_matches_oracle(bb):
+    xyz, etov = kuhn_cube_mesh(3)
+    s = bb.Solver(xyz, etov, 5, 2)
+    q = random_state(51, s.K, s.Np)
+    got = s.l2norm2(s.to_device(q))
+    o = Oracle(xyz, etov, 5, 2)
+    ref = o.l2_sq(o.bernstein_values_at_quad(q))
+    assert np.allclose(got, ref, rtol=1e-12)
+
+
+def _neighbourhood(nbr, seeds, rings):
+    sel = set(int(x) for x in seeds)
+    front = set(sel)
+    for _ in range(rings):
+        nxt = set()
+        for k in front:
+            for v in nbr[k]:
+                if v >= 0:
+                    nxt.add(int(v) >> 2)
+        front = nxt - sel
+        sel |= nxt
+    return np.array(sorted(sel))
+
+
+def _cube196k(bb, dtype):
+    xyz, etov = kuhn_cube_mesh(32)
+    s = bb.Solver(xyz, etov, 5, 2, dtype=dtype)
+    return xyz, etov, s
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_rhs_parity_on_sampled_elements(bb, dtype):
+    """196,608 tets, N=5, M=2, Gaussian-bump c^2, in the launch configuration the benchmark
+    times; the oracle recomputes the right-hand side of 300 sampled elements (each with its
+    face neighbours present, so their faces see the same traces)."""
+    print(f"[full-size rhs] {dtype}", flush=True)
+    xyz, etov, s = _cube196k(bb, dtype)
+    bumps = c2_gaussian_bumps(0)
+    s.project_c2(bumps)
+    q = random_state(61, s.K, s.Np)
+    out = s.rhs(s.to_device(q)).double().cpu().numpy()
+    rng = np.random.default_rng(62)
+    seeds = np.unique(np.concatenate([rng.choice(s.K, 290, replace=False), [0, 1, s.K - 1, s.K - 6]]))
+    nbr = s.geometry()["nbr"]
+    sub = _neighbourhood(nbr, seeds, 1)
+    o = Oracle(xyz, etov[sub], 5, 2)
+    o.set_c2_function(bumps, project=True)
+    R = o.rhs(o.from_bernstein(q[:, sub]))
+    pos = np.searchsorted(sub, seeds)
+    a = o.bernstein_values_at_quad(out[:, seeds])
+    b = o.values_at_quad(R[:, pos])
+    wJ = o.mesh.J[pos][:, None] * o.wq[None, :]
+    err = np.sqrt(np.sum((a - b) ** 2 * wJ, axis=(1, 2)) / np.sum(b ** 2 * wJ, axis=(1, 2)))
+    tol = FP64_TOL if dtype == "f64" else fp32_tol(5)
+    assert np.all(err < tol), err
+
+
+def test_full_size_step_parity_on_sampled_elements(bb):
+    """One full LSRK4 step at 196,608 tets, N=5, M=2 (FP64), Gaussian pulse, bump medium,
+    each side with its own projections: after five stages an element depends on its
+    5-ring, so the oracle steps the 5-ring sub-mesh of 6 sampled elements."""
+    import torch
+    print("[full-size step]", flush=True)
+    xyz, etov, s = _cube196k(bb, "f64")
+    bumps = c2_gaussian_bumps(0)
+    s.project_c2(bumps)
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    q0 = s.initial_state([ic_gaussian_pulse, zero, zero, zero])
+    dt = 5e-4  # below the CFL limit for h = 1/32, N = 5
+    q = s.to_device(q0)
+    res = torch.zeros_like(q)
+    s.step(q, res, dt, 1)
+    out = q.cpu().numpy()
+    K = s.K
+    # three elements at the pulse centre and three elsewhere
+    cen = xyz[etov].mean(axis=1)
+    d = np.linalg.norm(cen - 0.5, axis=1)
+    seeds = np.unique(np.concatenate([np.argsort(d)[:3], [5, K - 1, 12345]]))
+    nbr = s.geometry()["nbr"]
+    sub = _neighbourhood(nbr, seeds, 5)
+    o = Oracle(xyz, etov[sub], 5, 2)
+    o.set_c2_function(bumps, project=True)
+    Q0 = o.project_initial([ic_gaussian_pulse, zero, zero, zero])
+    Q, _ = o.step(Q0, np.zeros_like(Q0), dt, 1)
+    pos = np.searchsorted(sub, seeds)
+    a = o.bernstein_values_at_quad(out[:, seeds])
+    b = o.values_at_quad(Q[:, pos])
+    wJ = o.mesh.J[pos][:, None] * o.wq[None, :]
+    num = np.sum((a - b) ** 2 * wJ, axis=(1, 2))
+    den = np.maximum(np.sum(b ** 2 * wJ, axis=(1, 2)), 1e-300)
+    # fields that are exactly zero at the sampled elements are compared absolutely
+    err = np.where(den > 1e-200, np.sqrt(num / den), np.sqrt(num))
+    assert np.all(err < FP64_TOL), err
