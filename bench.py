@@ -106,9 +106,9 @@ def run_leg(s, q0, dt, steps, warmup):
     return q, ms, wall, copy_ms
 
 
-def cpu_baseline(dt):
+def cpu_baseline(dt, steps):
     """The oracle (dense quadrature WADG, FP64, NumPy/OpenBLAS) timed on a bounded sample:
-    the same workload on 16^3 cells x 6 = 24,576 tets, one LSRK4 step."""
+    the same workload on 16^3 cells x 6 = 24,576 tets, `steps` LSRK4 steps."""
     from threadpoolctl import threadpool_info
 
     from oracle import Oracle
@@ -120,13 +120,13 @@ def cpu_baseline(dt):
     zero = lambda x, y, z: 0.0 * x  # noqa: E731
     Q = o.project_initial([ic_gaussian_pulse, zero, zero, zero])
     t0 = time.perf_counter()
-    o.step(Q, np.zeros_like(Q), dt, 1)
+    o.step(Q, np.zeros_like(Q), dt, steps)
     t = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
     K = len(etov)
-    return {"value": K * dimp(N) * 4 / t / 1e9, "unit": "GDOF-updates/s", "cores": int(threads),
+    return {"value": K * dimp(N) * 4 * steps / t / 1e9, "unit": "GDOF-updates/s", "cores": int(threads),
             "kind": "oracle", "seconds": t,
-            "sample": f"cube 16^3x6 = {K} tets, N={N}, M={M}, same medium and pulse, 1 LSRK4 step, FP64"}
+            "sample": f"cube 16^3x6 = {K} tets, N={N}, M={M}, same medium and pulse, {steps} LSRK4 steps, FP64"}
 
 
 def main():
@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="time only the FP32 leg (profiling)")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter reference)")
+    ap.add_argument("--cpu-steps", type=int, default=15, help="LSRK4 steps of the CPU oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -205,7 +208,16 @@ def main():
     out["l2_error"] = {"fp64_vs_oracle": "<= 1e-11 relative L2 per field (parity tests)",
                        "fp32_vs_fp64": out.get("fp32", {}).get("rel_l2_vs_fp64_per_field")}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dt)
+        out["cpu_baseline"] = cpu_baseline(dt, args.cpu_steps)
+    if args.copy_ref_mib > 0:
+        import torch
+        n = args.copy_ref_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_ref"] = {"bytes_read": n * 8, "bytes_written": n * 8}
     print(json.dumps(out), flush=True)
 
 
