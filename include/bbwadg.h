@@ -14,9 +14,11 @@
  * B^N_alpha = N!/alpha! lambda^alpha) where the barycentric coordinates lambda_0..3
  * belong to the element's vertices SORTED BY ASCENDING GLOBAL VERTEX ID
  * (bbwadg_element_vertices returns that order), and alpha = (a0,a1,a2,a3) is
- * enumerated with a3 outermost (0..N), then a2 (0..N-a3), then a1 innermost
- * (0..N-a3-a2); a0 = N-a1-a2-a3. The same order is used for c^2 coefficients of
- * degree M: c2[K][Mp], Mp = (M+1)(M+2)(M+3)/6.
+ * enumerated graded by s = a1+a2+a3 (0..N), then a3 ascending, then a2 ascending
+ * (a1 = s-a2-a3, a0 = N-s); the index of (a1,a2,a3) is then
+ *     dimp(s-1) + a3 (2s+3-a3)/2 + a2,   dimp(n) = (n+1)(n+2)(n+3)/6, dimp(-1) = 0,
+ * independent of N. The same order is used for c^2 coefficients of degree M:
+ * c2[K][Mp], Mp = (M+1)(M+2)(M+3)/6.
  *
  * Ownership and streams
  * ---------------------

@@ -10,8 +10,9 @@ Test infrastructure only (see the package docstring).
   lambda_2 = (1+s)/2, lambda_3 = (1+t)/2.
 
 Coefficient order of Bernstein arrays (an interface format, shared with the library's
-documentation): alpha = (a0, a1, a2, a3), |alpha| = N, enumerated with a3 outermost
-(0..N), then a2 (0..N-a3), then a1 innermost (0..N-a3-a2); a0 = N - a1 - a2 - a3.
+documentation): alpha = (a0, a1, a2, a3), |alpha| = N, graded by s = a1 + a2 + a3
+(0..N); within one s, a3 ascending (outer) then a2 ascending (inner); a1 = s - a2 - a3,
+a0 = N - s. Face arrays: (b0, b1, b2) graded by t = b1 + b2, then b2 ascending.
 """
 from __future__ import annotations
 
@@ -156,19 +157,19 @@ def dubiner_tet(N: int, r, s, t, grad: bool = False):
 def multi_indices(N: int):
     """Multi-indices (a0, a1, a2, a3), |alpha| = N, in the documented coefficient order."""
     out = []
-    for a3 in range(N + 1):
-        for a2 in range(N - a3 + 1):
-            for a1 in range(N - a3 - a2 + 1):
-                out.append((N - a1 - a2 - a3, a1, a2, a3))
+    for s in range(N + 1):
+        for a3 in range(s + 1):
+            for a2 in range(s - a3 + 1):
+                out.append((N - s, s - a2 - a3, a2, a3))
     return out
 
 
 def multi_indices_2d(N: int):
-    """Face multi-indices (b0, b1, b2), |beta| = N, b2 outermost, b1 innermost."""
+    """Face multi-indices (b0, b1, b2), |beta| = N, in the documented order."""
     out = []
-    for b2 in range(N + 1):
-        for b1 in range(N - b2 + 1):
-            out.append((N - b1 - b2, b1, b2))
+    for t in range(N + 1):
+        for b2 in range(t + 1):
+            out.append((N - t, t - b2, b2))
     return out
 
 

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libbbwadg.so")
+# BBWADG_LIB selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("BBWADG_LIB") or os.path.join(_PKG, "libbbwadg.so")
 
 OK, EINVAL, EMESH, EC2, ENOMEM, EHIP = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1

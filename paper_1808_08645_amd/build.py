@@ -36,17 +36,21 @@ def _run(cmd):
     return p.stderr
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every HIP unit for gfx950 and link libbbwadg.so; returns its path."""
+def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str | None = None) -> str:
+    """Compile every HIP unit for gfx950 and link libbbwadg.so (or `out`); returns its path.
+
+    `defines` are extra -D options for the kernels (tuning variants)."""
     hipcc = _hipcc()
-    os.makedirs(BUILD, exist_ok=True)
+    lib = out or LIB
+    build_dir = BUILD if out is None else BUILD + "_" + os.path.basename(out).replace(".so", "")
+    os.makedirs(build_dir, exist_ok=True)
     units = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
     cmds = []
     for u in units:
-        obj = os.path.join(BUILD, u.replace(".hip", ".o"))
-        cmds.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, "-c",
+        obj = os.path.join(build_dir, u.replace(".hip", ".o"))
+        cmds.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *[f"-D{d}" for d in defines], "-c",
                      os.path.join(CSRC, u), "-o", obj])
-    host_obj = os.path.join(BUILD, "host.o")
+    host_obj = os.path.join(build_dir, "host.o")
     cmds.append([hipcc, "-x", "c++", *[c for c in COMMON if c not in ("-Xclang", "-target-feature",
                                                                        "-packed-fp32-ops")],
                  f"-I{_rocm()}/include", "-D__HIP_PLATFORM_AMD__",
@@ -57,10 +61,10 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
             if verbose and err.strip():
                 print(err, file=sys.stderr)
     objs = [c[c.index("-o") + 1] for c in cmds]
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

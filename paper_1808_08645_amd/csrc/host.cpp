@@ -47,37 +47,15 @@ ld binoml(int n, int k) {
   return r;
 }
 
-// Multi-indices of degree n in the documented coefficient order (a3 outermost, a1 innermost).
+// Multi-indices of degree n in the documented (graded) coefficient order: s = a1+a2+a3
+// ascending, then a3, then a2; the degree-n list is a prefix of the degree-(n+1) list
+// when compared by (a1, a2, a3).
 std::vector<std::array<int, 4>> mi3_list(int n) {
   std::vector<std::array<int, 4>> out;
-  for (int a3 = 0; a3 <= n; ++a3)
-    for (int a2 = 0; a2 <= n - a3; ++a2)
-      for (int a1 = 0; a1 <= n - a3 - a2; ++a1) out.push_back({n - a1 - a2 - a3, a1, a2, a3});
+  for (int s = 0; s <= n; ++s)
+    for (int a3 = 0; a3 <= s; ++a3)
+      for (int a2 = 0; a2 <= s - a3; ++a2) out.push_back({n - s, s - a2 - a3, a2, a3});
   return out;
-}
-// Face multi-indices (b0,b1,b2), b2 outermost, b1 innermost.
-std::vector<std::array<int, 3>> mi2_list(int n) {
-  std::vector<std::array<int, 3>> out;
-  for (int b2 = 0; b2 <= n; ++b2)
-    for (int b1 = 0; b1 <= n - b2; ++b1) out.push_back({n - b1 - b2, b1, b2});
-  return out;
-}
-int idx3(int n, int a1, int a2, int a3) {
-  if (a1 < 0 || a2 < 0 || a3 < 0 || a1 + a2 + a3 > n) return -1;
-  int s = 0;
-  for (int c = 0; c < a3; ++c) s += dim2(n - c);
-  for (int b = 0; b < a2; ++b) s += n - a3 - b + 1;
-  return s + a1;
-}
-int idx3(int n, const std::array<int, 4>& a) {
-  if (a[0] < 0 || a[0] + a[1] + a[2] + a[3] != n) return -1;
-  return idx3(n, a[1], a[2], a[3]);
-}
-int idx2(int n, const std::array<int, 3>& b) {
-  if (b[0] < 0 || b[1] < 0 || b[2] < 0 || b[0] + b[1] + b[2] != n) return -1;
-  int s = 0;
-  for (int c = 0; c < b[2]; ++c) s += n - c + 1;
-  return s + b[1];
 }
 
 // ------------------------------------------------------------- projection coefficients
@@ -246,131 +224,16 @@ void build_projector(int d, Projector& pr) {
 }
 
 // ------------------------------------------------------------------------ tables
+// The stage kernel derives all its index maps from the graded coefficient order; the
+// host only supplies the projection coefficients c_j.
 struct HostTables {
-  TableOffsets off{};
-  std::vector<uint16_t> tab;
-  std::vector<double> mulw;  // [dimp(N+M)][dimp(M)]
   double cj[kMaxN + 1] = {0};
-  double ell[kMaxN + 1] = {0};
 };
 
 void build_tables(int N, int M, HostTables& T) {
-  std::vector<uint16_t>& t = T.tab;
-  TableOffsets& o = T.off;
-  auto put4 = [&](int a, int b, int c, int d) {
-    t.push_back((uint16_t)a); t.push_back((uint16_t)b); t.push_back((uint16_t)c); t.push_back((uint16_t)d);
-  };
-  auto u16 = [](int v) { return v < 0 ? (int)kNone : v; };
-  for (int n = 0; n <= N + M; ++n) {
-    o.mi3[n] = (int)t.size();
-    for (auto& a : mi3_list(n)) put4(a[0], a[1], a[2], a[3]);
-  }
-  for (int n = 1; n <= N + M; ++n) {  // elevation n-1 -> n: gamma - e_k
-    o.el3[n] = (int)t.size();
-    for (auto& g : mi3_list(n)) {
-      int ix[4];
-      for (int k = 0; k < 4; ++k) {
-        auto h = g;
-        h[k] -= 1;
-        ix[k] = (g[k] > 0) ? idx3(n - 1, h) : -1;
-      }
-      put4(u16(ix[0]), u16(ix[1]), u16(ix[2]), u16(ix[3]));
-    }
-  }
-  for (int n = 1; n <= N + M; ++n) {  // reduction n -> n-1: alpha + e_k at degree n
-    o.red3[n] = (int)t.size();
-    for (auto& a : mi3_list(n - 1)) {
-      int ix[4];
-      for (int k = 0; k < 4; ++k) {
-        auto h = a;
-        h[k] += 1;
-        ix[k] = idx3(n, h);
-      }
-      put4(ix[0], ix[1], ix[2], ix[3]);
-    }
-  }
-  for (int n = 0; n <= N; ++n) {
-    o.mi2[n] = (int)t.size();
-    for (auto& b : mi2_list(n)) put4(b[0], b[1], b[2], 0);
-  }
-  o.el2 = (int)t.size();
-  for (auto& g : mi2_list(N)) {
-    int ix[3];
-    for (int k = 0; k < 3; ++k) {
-      auto h = g;
-      h[k] -= 1;
-      ix[k] = (g[k] > 0) ? idx2(N - 1, h) : -1;
-    }
-    put4(u16(ix[0]), u16(ix[1]), u16(ix[2]), kNone);
-  }
-  for (int n = 1; n <= N; ++n) {
-    o.red2[n] = (int)t.size();
-    for (auto& b : mi2_list(n - 1)) {
-      int ix[3];
-      for (int k = 0; k < 3; ++k) {
-        auto h = b;
-        h[k] += 1;
-        ix[k] = idx2(n, h);
-      }
-      put4(ix[0], ix[1], ix[2], kNone);
-    }
-  }
-  // face f is opposite local vertex f; its vertices in increasing local order u0<u1<u2
-  auto face_verts = [](int f, int u[3]) {
-    int m = 0;
-    for (int v = 0; v < 4; ++v)
-      if (v != f) u[m++] = v;
-  };
-  o.fidx = (int)t.size();
-  auto F2 = mi2_list(N);
-  for (int f = 0; f < 4; ++f) {
-    int u[3];
-    face_verts(f, u);
-    for (auto& b : F2) {
-      std::array<int, 4> a = {0, 0, 0, 0};
-      for (int m = 0; m < 3; ++m) a[u[m]] = b[m];
-      t.push_back((uint16_t)idx3(N, a));
-    }
-  }
-  while (t.size() % 4) t.push_back(0);
-  o.liftpos = (int)t.size();
-  int choff[kMaxN + 2];
-  choff[0] = 0;
-  for (int i = 0; i <= N; ++i) choff[i + 1] = choff[i] + dim2(N - i);
-  for (int f = 0; f < 4; ++f) {
-    int u[3];
-    face_verts(f, u);
-    for (auto& a : mi3_list(N)) {
-      int i = a[f];
-      std::array<int, 3> b = {a[u[0]], a[u[1]], a[u[2]]};
-      t.push_back((uint16_t)(choff[i] + idx2(N - i, b)));
-    }
-  }
-  while (t.size() % 4) t.push_back(0);
-  o.mulidx = (int)t.size();
-  auto H = mi3_list(N + M);
-  auto Bm = mi3_list(M);
-  T.mulw.assign(H.size() * Bm.size(), 0.0);
-  ld inv = 1.0L / binoml(N + M, N);
-  for (size_t g = 0; g < H.size(); ++g)
-    for (size_t b = 0; b < Bm.size(); ++b) {
-      std::array<int, 4> d;
-      bool ok = true;
-      ld wgt = inv;
-      for (int k = 0; k < 4; ++k) {
-        d[k] = H[g][k] - Bm[b][k];
-        if (d[k] < 0) ok = false;
-        else wgt *= binoml(H[g][k], Bm[b][k]);
-      }
-      t.push_back(ok ? (uint16_t)idx3(N, d) : kNone);
-      T.mulw[g * Bm.size() + b] = ok ? (double)wgt : 0.0;
-    }
-  while (t.size() % 4) t.push_back(0);
-  o.total = (int)t.size();
   ld c[kMaxN + 1];
   projection_cj(N, M, c);
   for (int j = 0; j <= N; ++j) T.cj[j] = (double)c[j];
-  for (int i = 0; i <= N; ++i) T.ell[i] = (double)((i % 2 ? -1.0L : 1.0L) * binoml(N, i) / (i + 1));
 }
 
 }  // namespace
@@ -398,8 +261,6 @@ struct bbwadg_ctx {
   void* d_geo = nullptr;
   void* d_conn = nullptr;
   void* d_c2 = nullptr;
-  void* d_tab = nullptr;
-  void* d_mulw = nullptr;
   void* d_q2 = nullptr;
   void* d_J = nullptr;
   void* d_mass = nullptr;
@@ -431,8 +292,7 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 }
 
 void free_device(bbwadg_ctx* c) {
-  void** ptrs[] = {&c->d_geo, &c->d_conn, &c->d_c2, &c->d_tab, &c->d_mulw, &c->d_q2,
-                   &c->d_J, &c->d_mass, &c->d_partial};
+  void** ptrs[] = {&c->d_geo, &c->d_conn, &c->d_c2, &c->d_q2, &c->d_J, &c->d_mass, &c->d_partial};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -494,17 +354,11 @@ StageArgs<real> make_args(const bbwadg_ctx* c) {
   a.geo = (const real*)c->d_geo;
   a.conn = (const int32_t*)c->d_conn;
   a.c2 = (const real*)c->d_c2;
-  a.tab = (const uint16_t*)c->d_tab;
-  a.mulw = (const real*)c->d_mulw;
-  a.off = c->tables.off;
   a.K = c->K;
   a.tau_p = (real)c->tau_p;
   a.tau_u = (real)c->tau_u;
   a.bc = c->bc;
-  for (int j = 0; j <= kMaxN; ++j) {
-    a.cj[j] = (real)c->tables.cj[j];
-    a.ell[j] = (real)c->tables.ell[j];
-  }
+  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
   return a;
 }
 
@@ -699,8 +553,7 @@ int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx**
   const size_t qbytes = (size_t)4 * K * c->Np * rs;
   c->nred_blocks = 1024;
   if ((rc = dmalloc(&c->d_geo, geo.size() * rs)) || (rc = dmalloc(&c->d_conn, c->conn.size() * 4)) ||
-      (rc = dmalloc(&c->d_c2, (size_t)K * c->Mp * rs)) || (rc = dmalloc(&c->d_tab, c->tables.tab.size() * 2)) ||
-      (rc = dmalloc(&c->d_mulw, c->tables.mulw.size() * rs)) || (rc = dmalloc(&c->d_q2, qbytes)) ||
+      (rc = dmalloc(&c->d_c2, (size_t)K * c->Mp * rs)) || (rc = dmalloc(&c->d_q2, qbytes)) ||
       (rc = dmalloc(&c->d_J, (size_t)K * 8)) || (rc = dmalloc(&c->d_mass, (size_t)c->Np * c->Np * 8)) ||
       (rc = dmalloc(&c->d_partial, (size_t)c->nred_blocks * 4 * 8))) {
     free_device(c);
@@ -711,14 +564,11 @@ int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx**
   std::vector<double> massd(mass.begin(), mass.end());
   if (rs == 8) {
     rc = upload(c->d_geo, geo.data(), geo.size() * 8);
-    if (!rc) rc = upload(c->d_mulw, c->tables.mulw.data(), c->tables.mulw.size() * 8);
   } else {
-    std::vector<float> gf = convert<float>(geo), mf = convert<float>(c->tables.mulw);
+    std::vector<float> gf = convert<float>(geo);
     rc = upload(c->d_geo, gf.data(), gf.size() * 4);
-    if (!rc) rc = upload(c->d_mulw, mf.data(), mf.size() * 4);
   }
   if (!rc) rc = upload(c->d_conn, c->conn.data(), c->conn.size() * 4);
-  if (!rc) rc = upload(c->d_tab, c->tables.tab.data(), c->tables.tab.size() * 2);
   if (!rc) rc = upload(c->d_J, c->J.data(), (size_t)K * 8);
   if (!rc) rc = upload(c->d_mass, massd.data(), massd.size() * 8);
   if (rc) { free_device(c); delete c; return rc; }

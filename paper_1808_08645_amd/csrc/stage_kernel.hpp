@@ -1,18 +1,28 @@
 // Fused BBWADG stage kernel for gfx950.
 //
-// One wavefront (64 lanes) owns EW consecutive elements; every intermediate lives in that
-// wave's slice of LDS, so the phases below synchronise at wavefront level only. Per
-// element and stage (paper eq. WADGform, Sections 4 and 5):
-//   volume   : reference derivatives at degree N-1 (two coefficients per derivative),
-//              combined with G = dr/dx, then one elevation back to degree N;
-//   surface  : upwind/penalty flux per face coefficient (Bernstein face basis functions
-//              vanish off their face, so traces are coefficient-wise), lift L^f = E_L L_0
-//              with L_0 = (2N+3)/2 I + N^2/2 E E^T and layer i scaled by l_i;
-//   WADG     : product with c^2_M (eq. mcoeff), M one-degree reductions, then the
-//              telescoped projection (eq. telescope) with the c_j of Theorem 5.1;
-//   update   : res = a res + dt rhs, q_out = q_in + b res (low-storage RK4 stage).
-// The state is read from qin (own coefficients and neighbour face traces) and written to
-// a different buffer, so no element can see a neighbour's updated trace.
+// One stage of the method for every element (paper eq. WADGform, Sections 4 and 5):
+//   volume  : reference derivatives at degree N-1 (two coefficients each), combined with
+//             G = dr/dx, then one degree elevation back to N (Section 4);
+//   surface : penalty flux per face coefficient (Bernstein face functions vanish off their
+//             face, so traces are coefficient-wise), lift L^f = E_L L_0 with
+//             L_0 = (2N+3)/2 I + N^2/2 E E^T and layer i scaled by l_i (Section 4);
+//   WADG    : product with c^2_M (eq. mcoeff), M one-degree reductions and the telescoped
+//             projection (eq. telescope) with the c_j of Theorem 5.1 (Section 5);
+//   update  : res = a res + dt rhs, q_out = q_in + b res (low-storage RK4 stage).
+//
+// Design for CDNA4:
+// * Coefficients use a graded order (by a1+a2+a3), so the degree-n coefficient list is a
+//   prefix of the degree-(n+1) list and a lane keeps the same multi-index at every
+//   degree. Each lane therefore computes its stencil neighbours (alpha +- e_k, face maps,
+//   lift positions, product positions) once, into registers; the element loop reads no
+//   index table.
+// * A wavefront owns EW elements at a time and keeps every intermediate in its own slice
+//   of LDS; phases synchronise at wavefront level only.
+// * Waves are persistent: each XCD processes a contiguous range of elements so that face
+//   neighbours are found in that XCD's L2, and the next element group's state, geometry
+//   and c^2 are prefetched into registers while the current one is computed.
+// * The state is read from qin and the next state written to qout (a different buffer),
+//   so no element ever reads a neighbour's updated trace.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,19 +37,61 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int lev_off(int N, int j) {
-  int s = 0;
-  for (int i = 0; i < j; ++i) s += dimp(N - i);
-  return s;
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Graded position of (a1, a2, a3): dimp(s-1) + a3 (2s+3-a3)/2 + a2, s = a1+a2+a3.
+__host__ __device__ constexpr int g3(int a1, int a2, int a3) {
+  return dimp(a1 + a2 + a3 - 1) + a3 * (2 * (a1 + a2 + a3) + 3 - a3) / 2 + a2;
 }
+// Graded face position of (b1, b2): t(t+1)/2 + b2, t = b1+b2.
+__host__ __device__ constexpr int g2(int b1, int b2) { return (b1 + b2) * (b1 + b2 + 1) / 2 + b2; }
+
+// Start of level i (degree N-i) in a concatenated face chain.
 constexpr int chain_off(int N, int i) {
   int s = 0;
   for (int l = 0; l < i; ++l) s += dim2(N - l);
   return s;
 }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// Start of level j (degree N-j) in the concatenated telescoping levels.
+constexpr int lev_off(int N, int j) {
+  int s = 0;
+  for (int i = 0; i < j; ++i) s += dimp(N - i);
+  return s;
+}
+__host__ __device__ constexpr long long fact(int n) {
+  long long r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+__host__ __device__ constexpr long long binom(int n, int k) {
+  return (k < 0 || k > n) ? 0 : fact(n) / (fact(k) * fact(n - k));
+}
+// l_i = (-1)^i C(N, i) / (i + 1): factor of lift layer i.
+__host__ __device__ constexpr double lift_ell(int N, int i) { return (i % 2 ? -1.0 : 1.0) * (double)binom(N, i) / (double)(i + 1); }
 
-// Elements per wavefront: pack small elements so that a wave's lanes are mostly busy.
+// Multi-index of graded position p: (a1, a2, a3).
+__device__ inline void pos3(int p, int& a1, int& a2, int& a3) {
+  int s = 0;
+  while (dimp(s) <= p) ++s;
+  int r = p - dimp(s - 1);
+  int c = 0;
+  while (r >= s - c + 1) {
+    r -= s - c + 1;
+    ++c;
+  }
+  a3 = c;
+  a2 = r;
+  a1 = s - r - c;
+}
+__device__ inline void pos2(int p, int& b1, int& b2) {
+  int t = 0;
+  while ((t + 1) * (t + 2) / 2 <= p) ++t;
+  b2 = p - t * (t + 1) / 2;
+  b1 = t - b2;
+}
+
+// Elements per wavefront: pack small elements so that most lanes are busy.
 template <int N>
 constexpr int elems_per_wave() {
   return dimp(N) <= 32 ? 64 / dimp(N) : 1;
@@ -50,381 +102,562 @@ struct StageLayout {
   static constexpr int NP = dimp(N), NP1 = dimp(N - 1), NFP = dim2(N), NFP1 = dim2(N - 1);
   static constexpr int NH = dimp(N + M), NH1 = dimp(N + M - 1), MP = dimp(M);
   static constexpr int LEV = lev_off(N, N + 1);
-  // per-wave LDS slices (in reals)
-  static constexpr int SQ = 0;                          // [4][EW][NP] own state
-  static constexpr int SC2 = SQ + 4 * EW * NP;          // [EW][MP]
-  static constexpr int SA = SC2 + EW * MP;              // volume [4][EW][NP1] | flux [2][4][EW][NFP] + [2][4][EW][NFP1]
-  static constexpr int SA_SIZE = cmax(4 * EW * NP1, 8 * EW * (NFP + NFP1));
-  static constexpr int SB = SA + SA_SIZE;               // lift chains [2][4][EW][NP] | WADG buffers
-  static constexpr int SB_SIZE = cmax(8 * EW * NP, EW * (NH + NH1 + LEV));
-  static constexpr int SR = SB + SB_SIZE;               // [EW][NP] r_p before the WADG step
-  static constexpr int TOTAL = SR + EW * NP;
+  static constexpr int PW = 25 + MP;                   // per-element scalars: geometry + c^2
+  static constexpr int S3 = cdiv(EW * NH, 64);         // 3D slots (degree <= N+M)
+  static constexpr int S3N = cdiv(EW * NP, 64);        // 3D slots covering degree N
+  static constexpr int S2 = cdiv(8 * EW * NFP, 64);    // face-chain slots (8 channels per element)
+  static constexpr int SF = cdiv(4 * EW * NFP, 64);    // flux slots (4 faces per element)
+  static constexpr int SPW = cdiv(EW * PW, 64);        // per-element scalar loads per lane
+  static constexpr int CH = 8 * EW;                    // chain channels: (p, u) x 4 faces x EW
+  // Per-wave LDS slice, in reals. A 3D array holds one real per unit pos*EW + e; a field
+  // array is 4 such planes. Face-chain arrays hold one real per unit b*CH + channel.
+  static constexpr int OFF_P = 0;                          // [EW][25] geometry, [EW][MP] c^2/beta!
+  static constexpr int OFF_Q = cdiv(EW * PW, 2) * 2;       // 4 planes [NP*EW] state; plane 0 later R
+  static constexpr int PLQ = EW * NP;
+  static constexpr int OFF_A = OFF_Q + 4 * PLQ;            // Y: 4 planes [NP1*EW] | F [NFP*CH], T [NFP1*CH]
+  static constexpr int PLY = EW * NP1;
+  static constexpr int SA = cmax(4 * PLY + EW * (NP - NP1), CH * (NFP + NFP1));
+  static constexpr int OFF_B = OFF_A + SA;                 // chain [NP*CH] | H, H1, levels
+  static constexpr int SB = cmax(CH * NP, EW * (NH + NH1 + LEV) + 4 * EW);
+  static constexpr int OFF_Z = OFF_B + SB;                 // a real that stays zero
+  static constexpr int TOTAL = cdiv(OFF_Z + 2, 2) * 2;
   static constexpr int BYTES = TOTAL * (int)sizeof(real);
-  // waves per workgroup: as many as fit in 64 KiB of LDS, at most 4
   static constexpr int WPB = cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
+  // product positions kept in registers when they are few, computed per use otherwise
+  static constexpr bool MUL_REGS = MP * S3 <= 24;
+  // waves per SIMD that LDS allows (160 KiB per CU, 4 SIMDs); registers are budgeted for
+  // the same occupancy, at most 4
+  static constexpr int LDS_WAVES = (163840 / (BYTES * WPB)) * WPB / 4;
+  static constexpr int WAVES_EU = LDS_WAVES < 1 ? 1 : (LDS_WAVES > 4 ? 4 : LDS_WAVES);
 };
 
+// Volume position of face coefficient (b0, b1, b2) of face f (face f is opposite local
+// vertex f; its vertices in increasing order carry b0, b1, b2).
+__device__ inline int face_pos(int f, int b0, int b1, int b2) {
+  switch (f) {
+    case 0: return g3(b0, b1, b2);
+    case 1: return g3(0, b1, b2);
+    case 2: return g3(b1, 0, b2);
+    default: return g3(b1, b2, 0);
+  }
+}
+
+// Optional occupancy target (waves per SIMD) for the register allocator; 0 leaves the
+// choice to the compiler.
+#ifndef BBW_WAVES_EU
+#define BBW_WAVES_EU 0
+#endif
+
 template <typename real, int N, int M, int EW, int WPB, bool UPDATE>
-__global__ __launch_bounds__(64 * WPB) void stage_kernel(const StageArgs<real> a) {
+__global__ __launch_bounds__(64 * WPB)
+#if BBW_WAVES_EU > 0
+__attribute__((amdgpu_waves_per_eu(BBW_WAVES_EU < StageLayout<real, N, M, EW>::WAVES_EU ? BBW_WAVES_EU : StageLayout<real, N, M, EW>::WAVES_EU, 8)))
+#endif
+void stage_kernel(const StageArgs<real> a) {
   using L = StageLayout<real, N, M, EW>;
-  constexpr int NP = L::NP, NP1 = L::NP1, NFP = L::NFP, NFP1 = L::NFP1;
-  constexpr int NH = L::NH, NH1 = L::NH1, MP = L::MP;
-  constexpr int NS = (EW * NP + 63) / 64;  // coefficient slots per lane
-  __shared__ real smem[WPB * L::TOTAL];
+  constexpr int NP = L::NP, NP1 = L::NP1, NFP = L::NFP, NFP1 = L::NFP1, NH = L::NH, MP = L::MP;
+  constexpr int S3 = L::S3, S3N = L::S3N, S2 = L::S2, SF = L::SF, SPW = L::SPW, PW = L::PW;
+  constexpr int CH = L::CH;
+  constexpr int SZ = (int)sizeof(real);
+  // byte offsets of the arrays inside a wave's slice
+  constexpr int BP = L::OFF_P * SZ, BQ = L::OFF_Q * SZ, BA = L::OFF_A * SZ, BB = L::OFF_B * SZ;
+  constexpr int BZ = L::OFF_Z * SZ;
+  constexpr int PQ = L::PLQ * SZ, PY = L::PLY * SZ;  // plane strides
+  __shared__ __attribute__((aligned(16))) real smem[WPB * L::TOTAL];
+  char* const lds = reinterpret_cast<char*>(smem);
+  auto at = [lds](int byteoff) -> real& { return *reinterpret_cast<real*>(lds + byteoff); };
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  real* const W = smem + wave * L::TOTAL;
-  real* const sq = W + L::SQ;
-  real* const sc2 = W + L::SC2;
-  real* const sA = W + L::SA;
-  real* const sB = W + L::SB;
-  real* const sR = W + L::SR;
+  const int wb = wave * L::TOTAL * SZ;  // this wave's slice
   const int64_t K = a.K;
-  const int64_t e0 = ((int64_t)blockIdx.x * WPB + wave) * EW;
-  const ushort4* const t4 = reinterpret_cast<const ushort4*>(a.tab);
-  const uint16_t* const t1 = a.tab;
   const real* const qin = a.qin;
 
-  // ---- load own state (and the RK register) -------------------------------------
-  real q[4][NS], acc[4][NS], rs[4][NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int v = lane + 64 * s;
-    const int e = v / NP, i = v - (v / NP) * NP;
-    const int64_t k = e0 + e;
-    const bool ok = (v < EW * NP) && (k < K);
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      const size_t g = ((size_t)f * K + k) * NP + i;
-      q[f][s] = ok ? qin[g] : real(0);
-      if constexpr (UPDATE) rs[f][s] = ok ? a.res[g] : real(0);
-      if (v < EW * NP) sq[(f * EW + e) * NP + i] = q[f][s];
-      acc[f][s] = real(0);
-    }
-  }
-  for (int v = lane; v < EW * MP; v += 64) {
-    const int e = v / MP, b = v - (v / MP) * MP;
-    const int64_t k = e0 + e;
-    sc2[v] = (k < K) ? a.c2[k * MP + b] : real(1);
-  }
-  wave_sync();
+  // ---- which element groups this wave owns: contiguous ranges per XCD ----------------
+  const int64_t ngroups = (K + EW - 1) / EW;
+  const int nxcd = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int xcd = blockIdx.x % nxcd;
+  const int64_t waves_per_xcd = (int64_t)(gridDim.x / nxcd) * WPB;
+  const int64_t lw = (int64_t)(blockIdx.x / nxcd) * WPB + wave;
+  const int64_t chunk = (ngroups + nxcd - 1) / nxcd;
+  const int64_t gbeg = xcd * chunk;
+  const int64_t gend = gbeg + chunk < ngroups ? gbeg + chunk : ngroups;
 
-  // ---- volume: reference derivatives at degree N-1 ---------------------------------
-  {
-    real* const sy = sA;  // [4][EW][NP1]: -d p/dx_i (i=0..2), -div u (3), scaled by N/2
-    const ushort4* up = t4 + a.off.red3[N] / 4;  // b + e_k at degree N, for b of degree N-1
-    constexpr real half_n = real(N) / real(2);
-    for (int v = lane; v < EW * NP1; v += 64) {
-      const int e = v / NP1, b = v - (v / NP1) * NP1;
-      const int64_t k = e0 + e;
-      real G[9];
+  // ---- per-lane index registers (byte offsets, computed once) -------------------------
+  // 3D slot s holds unit lane + 64 s = pos*EW + e with pos the graded position of
+  // (a1, a2, a3); up/dn are the units of alpha +- e_k (dn clamps to the unit itself when
+  // a_k = 0, where its weight is zero).
+  int pa3[S3], up3[S3][3], dn3[S3N][3];
+  real fac3[S3N], facH[S3];
+  int lp[S3N][4];
+  int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? MP : 1];
 #pragma unroll
-      for (int x = 0; x < 9; ++x) G[x] = (k < K) ? a.geo[k * kGeoStride + x] : real(0);
-      const ushort4 id = up[b];
-      const real* P = sq + (0 * EW + e) * NP;
-      real dp[3] = {P[id.y] - P[id.x], P[id.z] - P[id.x], P[id.w] - P[id.x]};
-      real div = 0;
+  for (int s = 0; s < S3; ++s) {
+    const int item = lane + 64 * s;
+    const int pos = item / EW, e = item - (item / EW) * EW;
+    int a1 = 0, a2 = 0, a3 = 0;
+    if (item < EW * NH) pos3(pos, a1, a2, a3);
+    const int sa = a1 + a2 + a3;
+    pa3[s] = a1 | (a2 << 8) | (a3 << 16) | (sa << 24);
+    up3[s][0] = wb + (g3(a1 + 1, a2, a3) * EW + e) * SZ;
+    up3[s][1] = wb + (g3(a1, a2 + 1, a3) * EW + e) * SZ;
+    up3[s][2] = wb + (g3(a1, a2, a3 + 1) * EW + e) * SZ;
+    const int a0N = N - sa, a0H = N + M - sa;
+    facH[s] = real(double(fact(a0H) * fact(a1) * fact(a2) * fact(a3)) / double(binom(N + M, N)));
+    if (s < S3N) {
+      const int sN = s < S3N ? s : 0;
+      dn3[sN][0] = wb + (a1 > 0 ? g3(a1 - 1, a2, a3) * EW + e : item) * SZ;
+      dn3[sN][1] = wb + (a2 > 0 ? g3(a1, a2 - 1, a3) * EW + e : item) * SZ;
+      dn3[sN][2] = wb + (a3 > 0 ? g3(a1, a2, a3 - 1) * EW + e : item) * SZ;
+      fac3[sN] = (a0N >= 0) ? real(1) / real(fact(a0N) * fact(a1) * fact(a2) * fact(a3)) : real(0);
+      const int af[4] = {a0N, a1, a2, a3};
+      const int b1f[4] = {a2, a2, a1, a1}, b2f[4] = {a3, a3, a3, a2};
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const real* U = sq + ((1 + i) * EW + e) * NP;
-        const real u0 = U[id.x];
-        div += G[3 * i + 0] * (U[id.y] - u0) + G[3 * i + 1] * (U[id.z] - u0) + G[3 * i + 2] * (U[id.w] - u0);
-      }
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-        sy[(i * EW + e) * NP1 + b] = -half_n * (G[3 * i] * dp[0] + G[3 * i + 1] * dp[1] + G[3 * i + 2] * dp[2]);
-      sy[(3 * EW + e) * NP1 + b] = -half_n * div;
+      for (int f = 0; f < 4; ++f)
+        lp[sN][f] = wb + ((af[f] >= 0 ? (chain_off(N, af[f]) + g2(b1f[f], b2f[f])) : 0) * CH + f * EW + e) * SZ;
     }
-  }
-  wave_sync();
-  // elevate to degree N: acc[0] = -div u, acc[1+i] = -d p / d x_i
-  {
-    const real* const sy = sA;
-    const ushort4* el = t4 + a.off.el3[N] / 4;
-    const ushort4* mi = t4 + a.off.mi3[N] / 4;
-    constexpr real inv_n = real(1) / real(N);
+    if constexpr (L::MUL_REGS) {
+      int b = 0;  // beta in the graded coefficient order of c^2
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int v = lane + 64 * s;
-      if (v < EW * NP) {
-        const int e = v / NP, i = v - (v / NP) * NP;
-        const ushort4 id = el[i];
-        const ushort4 m = mi[i];
-        const uint16_t ix[4] = {id.x, id.y, id.z, id.w};
-        const real w[4] = {real(m.x) * inv_n, real(m.y) * inv_n, real(m.z) * inv_n, real(m.w) * inv_n};
+      for (int sb = 0; sb <= M; ++sb)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const real* Y = sy + (c * EW + e) * NP1;
-          real t = 0;
+        for (int b3 = 0; b3 <= sb; ++b3)
 #pragma unroll
-          for (int k2 = 0; k2 < 4; ++k2)
-            if (ix[k2] != kNone) t += w[k2] * Y[ix[k2]];
-          acc[c == 3 ? 0 : c + 1][s] = t;
-        }
-      }
-    }
-  }
-  wave_sync();
-
-  // ---- surface: fluxes per face coefficient ------------------------------------------
-  real* const sF = sA;                      // [2][4][EW][NFP]
-  real* const sT = sA + 8 * EW * NFP;       // [2][4][EW][NFP1]
-  {
-    const uint16_t* fidx = t1 + a.off.fidx;
-    for (int v = lane; v < EW * 4 * NFP; v += 64) {
-      const int e = v / (4 * NFP);
-      const int r = v - e * (4 * NFP);
-      const int f = r / NFP, m = r - (r / NFP) * NFP;
-      const int64_t k = e0 + e;
-      const int own = fidx[f * NFP + m];
-      const real pm = sq[(0 * EW + e) * NP + own];
-      const real um = sq[(1 * EW + e) * NP + own];
-      const real vm = sq[(2 * EW + e) * NP + own];
-      const real wm = sq[(3 * EW + e) * NP + own];
-      real nx = 0, ny = 0, nz = 0;
-      int32_t nb = -1;
-      if (k < K) {
-        const real* g = a.geo + k * kGeoStride + 9 + 4 * f;
-        nx = g[1];
-        ny = g[2];
-        nz = g[3];
-        nb = a.conn[k * 4 + f];
-      }
-      real pp, up, vp, wp;
-      if (nb >= 0) {
-        const int64_t k2 = nb >> 2;
-        const int f2 = nb & 3;
-        const size_t base = (size_t)k2 * NP + fidx[f2 * NFP + m];
-        const size_t fs = (size_t)K * NP;
-        pp = qin[base];
-        up = qin[base + fs];
-        vp = qin[base + 2 * fs];
-        wp = qin[base + 3 * fs];
-      } else if (a.bc == 0) {  // p = 0 wall: p+ = -p, u+ = u
-        pp = -pm;
-        up = um;
-        vp = vm;
-        wp = wm;
-      } else {  // rigid wall: p+ = p, u+ = u - 2 (u.n) n
-        const real un = um * nx + vm * ny + wm * nz;
-        pp = pm;
-        up = um - 2 * un * nx;
-        vp = vm - 2 * un * ny;
-        wp = wm - 2 * un * nz;
-      }
-      const real jp = pp - pm;
-      const real jun = (up - um) * nx + (vp - vm) * ny + (wp - wm) * nz;
-      sF[((0 * 4 + f) * EW + e) * NFP + m] = real(0.5) * (a.tau_p * jp - jun);
-      sF[((1 * 4 + f) * EW + e) * NFP + m] = real(0.5) * (a.tau_u * jun - jp);
-    }
-  }
-  wave_sync();
-
-  // ---- lift: L_0 on each face, then the reduction chain ------------------------------
-  real* const sC = sB;  // [2][4][EW][NP]: chain levels 0..N of each face flux
-  {
-    const ushort4* red = t4 + a.off.red2[N] / 4;
-    const ushort4* mi = t4 + a.off.mi2[N - 1] / 4;
-    constexpr real inv_n = real(1) / real(N);
-    for (int v = lane; v < 8 * EW * NFP1; v += 64) {
-      const int c = v / NFP1, b = v - (v / NFP1) * NFP1;
-      const ushort4 id = red[b];
-      const ushort4 m = mi[b];
-      const real* F = sF + c * NFP;
-      sT[c * NFP1 + b] = inv_n * (real(m.x + 1) * F[id.x] + real(m.y + 1) * F[id.y] + real(m.z + 1) * F[id.z]);
-    }
-  }
-  wave_sync();
-  {
-    const ushort4* el = t4 + a.off.el2 / 4;
-    const ushort4* mi = t4 + a.off.mi2[N] / 4;
-    constexpr real inv_n = real(1) / real(N);
-    constexpr real l0a = real(2 * N + 3) / real(2);
-    constexpr real l0b = real(N * N) / real(2);
-    for (int v = lane; v < 8 * EW * NFP; v += 64) {
-      const int c = v / NFP, g = v - (v / NFP) * NFP;
-      const ushort4 id = el[g];
-      const ushort4 m = mi[g];
-      const real* T = sT + c * NFP1;
-      real t = 0;
-      if (id.x != kNone) t += real(m.x) * T[id.x];
-      if (id.y != kNone) t += real(m.y) * T[id.y];
-      if (id.z != kNone) t += real(m.z) * T[id.z];
-      sC[c * NP + g] = l0a * sF[c * NFP + g] + l0b * inv_n * t;
-    }
-  }
-  wave_sync();
-#pragma unroll
-  for (int i = 1; i <= N; ++i) {
-    const int n = N - i + 1;  // reduce degree n -> n-1
-    const ushort4* red = t4 + a.off.red2[n] / 4;
-    const ushort4* mi = t4 + a.off.mi2[n - 1] / 4;
-    const real inv_n = real(1) / real(n);
-    const int cnt = dim2(n - 1);
-    const int src = chain_off(N, i - 1), dst = chain_off(N, i);
-    for (int v = lane; v < 8 * EW * cnt; v += 64) {
-      const int c = v / cnt, b = v - (v / cnt) * cnt;
-      const ushort4 id = red[b];
-      const ushort4 m = mi[b];
-      const real* S = sC + c * NP + src;
-      sC[c * NP + dst + b] = inv_n * (real(m.x + 1) * S[id.x] + real(m.y + 1) * S[id.y] + real(m.z + 1) * S[id.z]);
-    }
-    wave_sync();
-  }
-  // gather the four face lifts into every coefficient
-  {
-    const uint16_t* lpos = t1 + a.off.liftpos;
-    const ushort4* mi = t4 + a.off.mi3[N] / 4;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int v = lane + 64 * s;
-      if (v < EW * NP) {
-        const int e = v / NP, i = v - (v / NP) * NP;
-        const int64_t k = e0 + e;
-        const ushort4 m = mi[i];
-        const uint16_t al[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          real sc = 0, nx = 0, ny = 0, nz = 0;
-          if (k < K) {
-            const real* g = a.geo + k * kGeoStride + 9 + 4 * f;
-            sc = g[0];
-            nx = g[1];
-            ny = g[2];
-            nz = g[3];
+          for (int b2 = 0; b2 <= sb - b3; ++b2) {
+            const int b1 = sb - b2 - b3, b0 = M - sb;
+            const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0H >= b0;
+            mpos[s][b] = wb + (ok ? BQ + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
+            ++b;
           }
-          const int pos = lpos[f * NP + i];
-          const real ell = a.ell[al[f]] * sc;
-          const real lp = sC[((0 * 4 + f) * EW + e) * NP + pos];
-          const real lu = sC[((1 * 4 + f) * EW + e) * NP + pos] * ell;
-          acc[0][s] += ell * lp;
-          acc[1][s] += nx * lu;
-          acc[2][s] += ny * lu;
-          acc[3][s] += nz * lu;
-        }
-        if constexpr (M > 0) sR[e * NP + i] = acc[0][s];
-        else acc[0][s] *= sc2[e * MP];
-      }
+    }
+  }
+  // face-chain slot t holds unit b*CH + ch with b the graded face position of (b1, b2)
+  int pb2[S2], up2[S2][2], dn2[S2][2];
+#pragma unroll
+  for (int t = 0; t < S2; ++t) {
+    const int item = lane + 64 * t;
+    const int b = item / CH, ch = item - (item / CH) * CH;
+    int b1 = 0, b2 = 0;
+    if (item < CH * NFP) pos2(b, b1, b2);
+    pb2[t] = b1 | (b2 << 8) | ((b1 + b2) << 16);
+    up2[t][0] = wb + (g2(b1 + 1, b2) * CH + ch) * SZ;
+    up2[t][1] = wb + (g2(b1, b2 + 1) * CH + ch) * SZ;
+    dn2[t][0] = wb + (b1 > 0 ? g2(b1 - 1, b2) * CH + ch : item) * SZ;
+    dn2[t][1] = wb + (b2 > 0 ? g2(b1, b2 - 1) * CH + ch : item) * SZ;
+  }
+  // flux slot u holds face coefficient m of face f of element e (unit m*4EW + f*EW + e)
+  int fown[SF], fnb[SF], ffe[SF];
+#pragma unroll
+  for (int u = 0; u < SF; ++u) {
+    const int item = lane + 64 * u;
+    const int m = item / (4 * EW), fe = item - (item / (4 * EW)) * (4 * EW);
+    const int f = fe / EW, e = fe - (fe / EW) * EW;
+    int b1 = 0, b2 = 0;
+    if (item < 4 * EW * NFP) pos2(m, b1, b2);
+    const int b0 = N - b1 - b2;
+    fown[u] = wb + (face_pos(f, b0, b1, b2) * EW + e) * SZ;
+    // the same face coefficient seen from a neighbour's face f2 (four 8-bit positions)
+    fnb[u] = face_pos(0, b0, b1, b2) | (face_pos(1, b0, b1, b2) << 8) | (face_pos(2, b0, b1, b2) << 16) |
+             (face_pos(3, b0, b1, b2) << 24);
+    ffe[u] = fe | (m << 16);
+  }
+  // factor 1/beta! of the c^2 coefficient this lane stages (product in scaled form)
+  real pscale[SPW];
+#pragma unroll
+  for (int r = 0; r < SPW; ++r) {
+    const int i = lane + 64 * r;
+    pscale[r] = real(1);
+    if (i >= 25 * EW && i < PW * EW) {
+      const int bpos = (i - 25 * EW) % MP;
+      int b1, b2, b3;
+      pos3(bpos, b1, b2, b3);
+      pscale[r] = real(1) / real(fact(M - b1 - b2 - b3) * fact(b1) * fact(b2) * fact(b3));
     }
   }
 
-  // ---- WADG: multiply by c^2_M, reduce M degrees, telescoped projection -------------
-  if constexpr (M > 0) {
-    wave_sync();
-    real* const sH = sB;               // [EW][NH]
-    real* const sH1 = sB + EW * NH;    // [EW][NH1]
-    real* const sL = sH1 + EW * NH1;   // [EW][LEV] levels j = 0..N of the telescoping
-    constexpr int LEV = L::LEV;
-    {
-      const uint16_t* mid = t1 + a.off.mulidx;
-      for (int v = lane; v < EW * NH; v += 64) {
-        const int e = v / NH, g = v - (v / NH) * NH;
-        real h = 0;
-#pragma unroll
-        for (int b = 0; b < MP; ++b) {
-          const uint16_t ix = mid[g * MP + b];
-          if (ix != kNone) h += a.mulw[g * MP + b] * sc2[e * MP + b] * sR[e * NP + ix];
-        }
-        sH[e * NH + g] = h;
-      }
-    }
-    wave_sync();
-    // M reductions: degree N+M -> N (the last lands in level 0 of sL)
-#pragma unroll
-    for (int n = N + M; n > N; --n) {
-      const int cnt = dimp(n - 1), srcn = dimp(n);
-      const real* src = ((N + M - n) % 2 == 0) ? sH : sH1;
-      real* dst = (n - 1 == N) ? sL : (((N + M - n) % 2 == 0) ? sH1 : sH);
-      const int dstride = (n - 1 == N) ? LEV : cnt;
-      const ushort4* red = t4 + a.off.red3[n] / 4;
-      const ushort4* mi = t4 + a.off.mi3[n - 1] / 4;
-      const real inv_n = real(1) / real(n);
-      for (int v = lane; v < EW * cnt; v += 64) {
-        const int e = v / cnt, b = v - (v / cnt) * cnt;
-        const ushort4 id = red[b];
-        const ushort4 m = mi[b];
-        const real* S = src + e * srcn;
-        dst[e * dstride + b] = inv_n * (real(m.x + 1) * S[id.x] + real(m.y + 1) * S[id.y] +
-                                         real(m.z + 1) * S[id.z] + real(m.w + 1) * S[id.w]);
-      }
-      wave_sync();
-    }
-    // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1
-#pragma unroll
-    for (int j = 1; j <= N; ++j) {
-      const int n = N - j + 1;
-      const int cnt = dimp(n - 1);
-      const ushort4* red = t4 + a.off.red3[n] / 4;
-      const ushort4* mi = t4 + a.off.mi3[n - 1] / 4;
-      const real inv_n = real(1) / real(n);
-      const int src = lev_off(N, j - 1), dst = lev_off(N, j);
-      for (int v = lane; v < EW * cnt; v += 64) {
-        const int e = v / cnt, b = v - (v / cnt) * cnt;
-        const ushort4 id = red[b];
-        const ushort4 m = mi[b];
-        const real* S = sL + e * LEV + src;
-        sL[e * LEV + dst + b] = inv_n * (real(m.x + 1) * S[id.x] + real(m.y + 1) * S[id.y] +
-                                         real(m.z + 1) * S[id.z] + real(m.w + 1) * S[id.w]);
-      }
-      wave_sync();
-    }
-    // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}
-    for (int v = lane; v < EW; v += 64) sL[v * LEV + lev_off(N, N)] *= a.cj[N];
-    wave_sync();
-#pragma unroll
-    for (int j = N - 1; j >= 0; --j) {
-      const int n = N - j;  // degree of level j
-      const int cnt = dimp(n);
-      const ushort4* el = t4 + a.off.el3[n] / 4;
-      const ushort4* mi = t4 + a.off.mi3[n] / 4;
-      const real inv_n = real(1) / real(n);
-      const real cj = a.cj[j];
-      const int lo = lev_off(N, j), hi = lev_off(N, j + 1);
-      for (int v = lane; v < EW * cnt; v += 64) {
-        const int e = v / cnt, g = v - (v / cnt) * cnt;
-        const ushort4 id = el[g];
-        const ushort4 m = mi[g];
-        const real* S = sL + e * LEV + hi;
-        real t = 0;
-        if (id.x != kNone) t += real(m.x) * S[id.x];
-        if (id.y != kNone) t += real(m.y) * S[id.y];
-        if (id.z != kNone) t += real(m.z) * S[id.z];
-        if (id.w != kNone) t += real(m.w) * S[id.w];
-        real* D = sL + e * LEV + lo + g;
-        *D = cj * (*D) + inv_n * t;
-      }
-      wave_sync();
-    }
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int v = lane + 64 * s;
-      if (v < EW * NP) {
-        const int e = v / NP, i = v - (v / NP) * NP;
-        acc[0][s] = sL[e * LEV + i];
-      }
-    }
-  }
+  // zero this wave's LDS slice once (stale reads are weighted by zero and must be finite)
+  for (int i = lane; i < L::TOTAL; i += 64) at(wb + i * SZ) = real(0);
+  wave_sync();
 
-  // ---- write: rhs, or the low-storage RK stage ----------------------------------------
+  // ---- prefetch of the next element group ------------------------------------------------
+  real qn[4][S3N], pn[SPW];
+  int cn[SF];
+  auto prefetch = [&](int64_t g) {
+    const int64_t k0 = g * EW;
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int v = lane + 64 * s;
-    const int e = v / NP, i = v - (v / NP) * NP;
-    const int64_t k = e0 + e;
-    if (v < EW * NP && k < K) {
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
+      const int e = item - (item / EW) * EW, pos = item / EW;
+      const bool ok = item < EW * NP && k0 + e < K;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) qn[f][s] = ok ? qin[((size_t)f * K + k0 + e) * NP + pos] : real(0);
+    }
+#pragma unroll
+    for (int r = 0; r < SPW; ++r) {
+      const int i = lane + 64 * r;
+      real v = real(0);
+      if (i < 25 * EW) {
+        if (k0 + i / 25 < K) v = a.geo[k0 * kGeoStride + i];
+      } else if (i < PW * EW) {
+        const int j = i - 25 * EW;
+        if (k0 + j / MP < K) v = a.c2[k0 * MP + j];
+      }
+      pn[r] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < SF; ++u) {
+      const int item = lane + 64 * u;
+      const int fe = ffe[u] & 0xFFFF, f = fe / EW, e = fe - (fe / EW) * EW;
+      cn[u] = (item < 4 * EW * NFP && k0 + e < K) ? a.conn[(k0 + e) * 4 + f] : -1;
+    }
+  };
+
+  int64_t g = gbeg + lw;
+  if (g < gend) prefetch(g);
+
+  for (; g < gend; g += waves_per_xcd) {
+    const int64_t k0 = g * EW;
+    // ---- stage this group's scalars and state into LDS --------------------------------
+#pragma unroll
+    for (int r = 0; r < SPW; ++r) {
+      const int i = lane + 64 * r;
+      if (i < PW * EW) at(wb + BP + i * SZ) = pn[r] * pscale[r];
+    }
+    real q[4][S3N];
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const size_t g = ((size_t)f * K + k) * NP + i;
-        if constexpr (UPDATE) {
-          const real r = a.rk_a * rs[f][s] + a.dt * acc[f][s];
-          a.res[g] = r;
-          a.qout[g] = q[f][s] + a.rk_b * r;
-        } else {
-          a.qout[g] = acc[f][s];
+        q[f][s] = qn[f][s];
+        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = q[f][s];
+      }
+    }
+    // ---- issue this group's RK register and neighbour traces, then the next prefetch ----
+    real rs[4][S3N];
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
+      const int e = item - (item / EW) * EW, pos = item / EW;
+      const bool ok = item < EW * NP && k0 + e < K;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if constexpr (UPDATE) rs[f][s] = ok ? a.res[((size_t)f * K + k0 + e) * NP + pos] : real(0);
+        else rs[f][s] = real(0);
+      }
+    }
+    real nb[4][SF];
+    int cur_conn[SF];
+#pragma unroll
+    for (int u = 0; u < SF; ++u) {
+      const int c = cn[u];
+      cur_conn[u] = c;
+      if (c >= 0) {
+        const size_t base = (size_t)(c >> 2) * NP + ((fnb[u] >> (8 * (c & 3))) & 255);
+        const size_t fs = (size_t)K * NP;
+        nb[0][u] = qin[base];
+        nb[1][u] = qin[base + fs];
+        nb[2][u] = qin[base + 2 * fs];
+        nb[3][u] = qin[base + 3 * fs];
+      } else {
+        nb[0][u] = nb[1][u] = nb[2][u] = nb[3][u] = real(0);
+      }
+    }
+    const int64_t gnext = g + waves_per_xcd;
+    if (gnext < gend) prefetch(gnext);
+    wave_sync();
+
+    // ---- volume: reference derivatives at degree N-1 -----------------------------------
+    // Y planes: -dp/dx, -dp/dy, -dp/dz, -div u at degree N-1 (times N/2)
+    constexpr real half_n = real(N) / real(2);
+#pragma unroll
+    for (int s = 0; s < S3; ++s) {
+      const int item = lane + 64 * s;
+      if (s * 64 < EW * NP1 && item < EW * NP1) {
+        const int e = item - (item / EW) * EW;
+        const int gm = wb + BP + e * 25 * SZ;
+        const int self = wb + item * SZ;
+        real v0[4], v1[4], v2[4], v3[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          v0[f] = at(self + BQ + f * PQ);
+          v1[f] = at(up3[s][0] + BQ + f * PQ);
+          v2[f] = at(up3[s][1] + BQ + f * PQ);
+          v3[f] = at(up3[s][2] + BQ + f * PQ);
+        }
+        real dv = 0;
+        real gr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const real G0 = at(gm + (3 * i) * SZ), G1 = at(gm + (3 * i + 1) * SZ), G2 = at(gm + (3 * i + 2) * SZ);
+          gr[i] = -half_n * (G0 * (v1[0] - v0[0]) + G1 * (v2[0] - v0[0]) + G2 * (v3[0] - v0[0]));
+          dv += G0 * (v1[1 + i] - v0[1 + i]) + G1 * (v2[1 + i] - v0[1 + i]) + G2 * (v3[1 + i] - v0[1 + i]);
+        }
+        at(self + BA + 0 * PY) = gr[0];
+        at(self + BA + 1 * PY) = gr[1];
+        at(self + BA + 2 * PY) = gr[2];
+        at(self + BA + 3 * PY) = -half_n * dv;
+      }
+    }
+    wave_sync();
+    // elevate to degree N: acc[0] = -div u, acc[1 + i] = -d p / d x_i
+    real acc[4][S3N] = {};
+    constexpr real inv_n = real(1) / real(N);
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
+      if (item >= EW * NP) continue;
+      const int self = wb + item * SZ;
+      const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+      const real w0 = real(N - sa) * inv_n, w1 = real(a1) * inv_n, w2 = real(a2) * inv_n, w3 = real(a3) * inv_n;
+      real t[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        t[c] = w0 * at(self + BA + c * PY) + w1 * at(dn3[s][0] + BA + c * PY) + w2 * at(dn3[s][1] + BA + c * PY) +
+               w3 * at(dn3[s][2] + BA + c * PY);
+      acc[0][s] = t[3];
+      acc[1][s] = t[0];
+      acc[2][s] = t[1];
+      acc[3][s] = t[2];
+    }
+    wave_sync();
+
+    // ---- surface: penalty fluxes per face coefficient ------------------------------------
+    // F [NFP*CH] at BA, channel (type*4 + f)*EW + e; T [NFP1*CH] right after it
+    constexpr int BF = BA, BT = BA + CH * NFP * SZ;
+#pragma unroll
+    for (int u = 0; u < SF; ++u) {
+      const int item = lane + 64 * u;
+      if (item < 4 * EW * NFP) {
+        const int fe = ffe[u] & 0xFFFF, m = ffe[u] >> 16;
+        const int f = fe / EW, e = fe - (fe / EW) * EW;
+        const real pm = at(fown[u] + BQ), um = at(fown[u] + BQ + PQ), vm = at(fown[u] + BQ + 2 * PQ),
+                   wm = at(fown[u] + BQ + 3 * PQ);
+        const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
+        const real nx = at(gf + SZ), ny = at(gf + 2 * SZ), nz = at(gf + 3 * SZ);
+        real pp, up, vp, wp;
+        if (cur_conn[u] >= 0) {
+          pp = nb[0][u];
+          up = nb[1][u];
+          vp = nb[2][u];
+          wp = nb[3][u];
+        } else if (a.bc == 0) {  // p = 0 wall: p+ = -p, u+ = u
+          pp = -pm;
+          up = um;
+          vp = vm;
+          wp = wm;
+        } else {  // rigid wall: p+ = p, u+ = u - 2 (u.n) n
+          const real un = um * nx + vm * ny + wm * nz;
+          pp = pm;
+          up = um - 2 * un * nx;
+          vp = vm - 2 * un * ny;
+          wp = wm - 2 * un * nz;
+        }
+        const real jp = pp - pm;
+        const real jun = (up - um) * nx + (vp - vm) * ny + (wp - wm) * nz;
+        const int dst = wb + BF + (m * CH + fe) * SZ;
+        at(dst) = real(0.5) * (a.tau_p * jp - jun);
+        at(dst + 4 * EW * SZ) = real(0.5) * (a.tau_u * jun - jp);
+      }
+    }
+    wave_sync();
+
+    // ---- lift: L_0 on each face flux, then the layer chain (levels pre-scaled by l_i) -----
+#pragma unroll
+    for (int t = 0; t < S2; ++t) {  // T = (E^N_{N-1})^T F
+      const int item = lane + 64 * t;
+      if (t * 64 < CH * NFP1 && item < CH * NFP1) {
+        const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
+        const int self = wb + item * SZ;
+        at(self + BT) = inv_n * (real(N - tb) * at(self + BF) + real(b1 + 1) * at(up2[t][0] + BF) +
+                                 real(b2 + 1) * at(up2[t][1] + BF));
+      }
+    }
+    wave_sync();
+    constexpr int BC = BB;  // chain [NP*CH], level i at chain_off(N, i)*CH
+    {
+      constexpr real l0a = real(2 * N + 3) / real(2);
+      constexpr real l0b = real(N * N) / real(2) / real(N);
+#pragma unroll
+      for (int t = 0; t < S2; ++t) {  // level 0 = L_0 F = (2N+3)/2 F + N^2/2 E T
+        const int item = lane + 64 * t;
+        if (item < CH * NFP) {
+          const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
+          const int self = wb + item * SZ;
+          const real et = real(N - tb) * at(self + BT) + real(b1) * at(dn2[t][0] + BT) + real(b2) * at(dn2[t][1] + BT);
+          at(self + BC) = l0a * at(self + BF) + l0b * et;
         }
       }
     }
+    wave_sync();
+#pragma unroll
+    for (int i = 1; i <= N; ++i) {
+      const int n = N - i + 1;  // level i-1 has degree n
+      const real sc = real(lift_ell(N, i) / lift_ell(N, i - 1)) / real(n);
+      const int cnt = CH * dim2(n - 1);
+      const int src = BC + chain_off(N, i - 1) * CH * SZ, dst = BC + chain_off(N, i) * CH * SZ;
+#pragma unroll
+      for (int t = 0; t < S2; ++t) {
+        const int item = lane + 64 * t;
+        if (t * 64 < cnt && item < cnt) {
+          const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
+          const int self = wb + item * SZ;
+          at(self + dst) = sc * (real(n - tb) * at(self + src) + real(b1 + 1) * at(up2[t][0] + src) +
+                                 real(b2 + 1) * at(up2[t][1] + src));
+        }
+      }
+      wave_sync();
+    }
+    // gather the four face lifts into every coefficient
+    constexpr int BR = BQ;  // r_p / alpha! (degree N), in the first state plane
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
+      if (item < EW * NP) {
+        const int e = item - (item / EW) * EW;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
+          const real sc = at(gf);
+          const real lpv = at(lp[s][f] + BC);
+          const real luv = at(lp[s][f] + BC + 4 * EW * SZ) * sc;
+          acc[0][s] += sc * lpv;
+          acc[1][s] += at(gf + SZ) * luv;
+          acc[2][s] += at(gf + 2 * SZ) * luv;
+          acc[3][s] += at(gf + 3 * SZ) * luv;
+        }
+        if constexpr (M > 0) {
+          at(wb + BR + item * SZ) = acc[0][s] * fac3[s];
+        } else {
+          acc[0][s] *= at(wb + BP + (25 * EW + e * MP) * SZ);
+        }
+      }
+    }
+
+    // ---- WADG: product with c^2_M, M reductions, telescoped projection -----------------
+    if constexpr (M > 0) {
+      wave_sync();
+      constexpr int NH1 = L::NH1;
+      constexpr int BH = BB, BH1 = BB + EW * NH * SZ, BL = BH1 + EW * NH1 * SZ;
+#pragma unroll
+      for (int s = 0; s < S3; ++s) {
+        const int item = lane + 64 * s;
+        if (item < EW * NH) {
+          const int e = item - (item / EW) * EW;
+          const int c2s = wb + BP + (25 * EW + e * MP) * SZ;
+          real h = 0;
+          if constexpr (L::MUL_REGS) {
+#pragma unroll
+            for (int b = 0; b < MP; ++b) h += at(mpos[s][b]) * at(c2s + b * SZ);
+          } else {
+            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+            const int a0 = N + M - sa;
+            int b = 0;  // beta in the graded coefficient order of c^2
+#pragma unroll
+            for (int sb = 0; sb <= M; ++sb)
+#pragma unroll
+              for (int b3 = 0; b3 <= sb; ++b3)
+#pragma unroll
+                for (int b2 = 0; b2 <= sb - b3; ++b2) {
+                  const int b1 = sb - b2 - b3, b0 = M - sb;
+                  const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0 >= b0;
+                  const int p = wb + (ok ? BR + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
+                  h += at(p) * at(c2s + b * SZ);
+                  ++b;
+                }
+          }
+          at(wb + BH + item * SZ) = h * facH[s];
+        }
+      }
+      wave_sync();
+      // M reductions: degree N+M -> N; the last one writes level 0 of the telescoping
+#pragma unroll
+      for (int n = N + M; n > N; --n) {
+        const int src = ((N + M - n) % 2 == 0) ? BH : BH1;
+        const int dst = (n - 1 == N) ? BL : (((N + M - n) % 2 == 0) ? BH1 : BH);
+        const real inv = real(1) / real(n);
+        const int cnt = EW * dimp(n - 1);
+#pragma unroll
+        for (int s = 0; s < S3; ++s) {
+          const int item = lane + 64 * s;
+          if (s * 64 < cnt && item < cnt) {
+            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+            const int self = wb + item * SZ;
+            at(self + dst) = inv * (real(n - sa) * at(self + src) + real(a1 + 1) * at(up3[s][0] + src) +
+                                    real(a2 + 1) * at(up3[s][1] + src) + real(a3 + 1) * at(up3[s][2] + src));
+          }
+        }
+        wave_sync();
+      }
+      // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1
+#pragma unroll
+      for (int j = 1; j <= N; ++j) {
+        const int n = N - j + 1;
+        const real inv = real(1) / real(n);
+        const int cnt = EW * dimp(n - 1);
+        const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
+#pragma unroll
+        for (int s = 0; s < S3N; ++s) {
+          const int item = lane + 64 * s;
+          if (s * 64 < cnt && item < cnt) {
+            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+            const int self = wb + item * SZ;
+            at(self + dst) = inv * (real(n - sa) * at(self + src) + real(a1 + 1) * at(up3[s][0] + src) +
+                                    real(a2 + 1) * at(up3[s][1] + src) + real(a3 + 1) * at(up3[s][2] + src));
+          }
+        }
+        wave_sync();
+      }
+      // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}
+      if (lane < EW) at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) *= a.cj[N];
+      wave_sync();
+#pragma unroll
+      for (int j = N - 1; j >= 0; --j) {
+        const int n = N - j;
+        const real inv = real(1) / real(n);
+        const real cj = a.cj[j];
+        const int cnt = EW * dimp(n);
+        const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
+#pragma unroll
+        for (int s = 0; s < S3N; ++s) {
+          const int item = lane + 64 * s;
+          if (s * 64 < cnt && item < cnt) {
+            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+            const int self = wb + item * SZ;
+            const real el = real(n - sa) * at(self + hi) + real(a1) * at(dn3[s][0] + hi) +
+                            real(a2) * at(dn3[s][1] + hi) + real(a3) * at(dn3[s][2] + hi);
+            at(self + lo) = cj * at(self + lo) + inv * el;
+          }
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int s = 0; s < S3N; ++s) {
+        const int item = lane + 64 * s;
+        if (item < EW * NP) acc[0][s] = at(wb + BL + item * SZ);
+      }
+    }
+
+    // ---- write: rhs, or the low-storage RK stage --------------------------------------------
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + 64 * s;
+      const int e = item - (item / EW) * EW, pos = item / EW;
+      if (item < EW * NP && k0 + e < K) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const size_t gi = ((size_t)f * K + k0 + e) * NP + pos;
+          if constexpr (UPDATE) {
+            const real r = a.rk_a * rs[f][s] + a.dt * acc[f][s];
+            a.res[gi] = r;
+            a.qout[gi] = q[f][s] + a.rk_b * r;
+          } else {
+            a.qout[gi] = acc[f][s];
+          }
+        }
+      }
+    }
+    wave_sync();  // the next group overwrites this wave's LDS slice
   }
 }
 
@@ -433,11 +666,24 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
   constexpr int EW = elems_per_wave<N>();
   using L = StageLayout<real, N, M, EW>;
   constexpr int WPB = L::WPB;
-  const int64_t per_block = (int64_t)EW * WPB;
-  const int64_t blocks = (a.K + per_block - 1) / per_block;
+  auto kern = stage_kernel<real, N, M, EW, WPB, UPDATE>;
+  static int grid = 0;  // persistent grid: resident blocks on the device, a multiple of 8
+  if (grid == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPB, 0);
+    if (ncu <= 0) ncu = 256;
+    if (per_cu <= 0) per_cu = 1;
+    grid = ncu * per_cu;
+    grid = (grid / 8) * 8 > 0 ? (grid / 8) * 8 : grid;
+  }
+  const int64_t groups = (a.K + EW - 1) / EW;
+  const int64_t need = (groups + WPB - 1) / WPB;
+  int blocks = grid;
+  if (need < blocks) blocks = (int)(need >= 8 ? (need / 8) * 8 : need);
   if (blocks <= 0) return 0;
-  hipLaunchKernelGGL((stage_kernel<real, N, M, EW, WPB, UPDATE>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
-                     (hipStream_t)stream, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * WPB), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
@@ -488,10 +734,6 @@ int launch_l2norm_typed(const void* q, int64_t K, const double* J, const double*
                      (const real*)q, K, J, mass, partial);
   return (int)hipGetLastError();
 }
-
-}  // namespace bbw
-
-namespace bbw {
 
 template <int N, int M>
 int dispatch_nm(bool update, bool f64, const void* args, void* stream) {
