@@ -27,6 +27,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "bbwadg_internal.hpp"
 
 namespace bbw {
@@ -669,11 +672,19 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
   auto kern = stage_kernel<real, N, M, EW, WPB, UPDATE>;
   static int grid = 0;  // persistent grid: resident blocks on the device, a multiple of 8
   if (grid == 0) {
-    int dev = 0, ncu = 0, per_cu = 0;
+    int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPB, 0);
     if (ncu <= 0) ncu = 256;
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WPB, 0);
+    if (getenv("BBWADG_DEBUG")) {
+      hipFuncAttributes attr{};
+      (void)hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(kern));
+      fprintf(stderr, "bbwadg: N=%d M=%d sizeof(real)=%d WPB=%d occupancy blocks/CU=%d numRegs=%d lds=%zu\n", N, M,
+              (int)sizeof(real), WPB, per_cu, attr.numRegs, (size_t)attr.sharedSizeBytes);
+    }
+    if (const char* env = getenv("BBWADG_BLOCKS_PER_CU")) per_cu = atoi(env);  // tuning override
     if (per_cu <= 0) per_cu = 1;
     grid = ncu * per_cu;
     grid = (grid / 8) * 8 > 0 ? (grid / 8) * 8 : grid;
