@@ -59,6 +59,12 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime; load it first so that this library binds to the same
+    # one (both share the runtime's soname) and device pointers and streams agree.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pd, pi32, pi64 = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
@@ -118,6 +124,12 @@ class Solver:
                  tau_u: float = 1.0, bc: str = "p0", host_only: bool = False):
         self._lib = load_library()
         self._ctx = C.c_void_p()
+        if not host_only:
+            # torch owns the device buffers and streams: initialise its runtime first
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("a HIP device is needed (use host_only=True for setup-only contexts)")
+            torch.cuda.current_device()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._etov = np.ascontiguousarray(etov, dtype=np.int32)
         if self._xyz.ndim != 2 or self._xyz.shape[1] != 3 or self._etov.ndim != 2 or self._etov.shape[1] != 4:

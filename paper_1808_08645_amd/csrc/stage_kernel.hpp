@@ -41,6 +41,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// An opaque copy: the compiler may neither hoist work derived from it out of a loop nor
+// share such work between uses (recomputing a few integer ops beats holding registers).
+__device__ __forceinline__ int opq(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Graded position of (a1, a2, a3): dimp(s-1) + a3 (2s+3-a3)/2 + a2, s = a1+a2+a3.
@@ -94,43 +101,56 @@ __device__ inline void pos2(int p, int& b1, int& b2) {
   b1 = t - b2;
 }
 
-// Elements per wavefront: pack small elements so that most lanes are busy.
+// Elements per team: pack small elements so that most lanes are busy.
 template <int N>
 constexpr int elems_per_wave() {
   return dimp(N) <= 32 ? 64 / dimp(N) : 1;
 }
+// Waves per team: large elements are shared by up to four wavefronts so that each lane
+// carries at most a few coefficients.
+template <int N>
+constexpr int waves_per_team() {
+  return dimp(N) <= 64 ? 1 : (dimp(N) + 63) / 64 > 4 ? 4 : (dimp(N) + 63) / 64;
+}
 
 template <typename real, int N, int M, int EW>
 struct StageLayout {
+  static constexpr int TW = waves_per_team<N>();     // waves per team (one team owns EW elements)
+  static constexpr int TL = 64 * TW;                   // lanes per team
   static constexpr int NP = dimp(N), NP1 = dimp(N - 1), NFP = dim2(N), NFP1 = dim2(N - 1);
   static constexpr int NH = dimp(N + M), NH1 = dimp(N + M - 1), MP = dimp(M);
   static constexpr int LEV = lev_off(N, N + 1);
   static constexpr int PW = 25 + MP;                   // per-element scalars: geometry + c^2
-  static constexpr int S3 = cdiv(EW * NH, 64);         // 3D slots (degree <= N+M)
-  static constexpr int S3N = cdiv(EW * NP, 64);        // 3D slots covering degree N
-  static constexpr int S2 = cdiv(8 * EW * NFP, 64);    // face-chain slots (8 channels per element)
-  static constexpr int SF = cdiv(4 * EW * NFP, 64);    // flux slots (4 faces per element)
-  static constexpr int SPW = cdiv(EW * PW, 64);        // per-element scalar loads per lane
+  static constexpr int S3 = cdiv(EW * NH, TL);         // 3D slots (degree <= N+M)
+  static constexpr int S3N = cdiv(EW * NP, TL);        // 3D slots covering degree N
+  static constexpr int S2 = cdiv(8 * EW * NFP, TL);    // face-chain slots (8 channels per element)
+  static constexpr int SF = cdiv(4 * EW * NFP, TL);    // flux slots (4 faces per element)
+  static constexpr int SPW = cdiv(EW * PW, TL);        // per-element scalar loads per lane
   static constexpr int CH = 8 * EW;                    // chain channels: (p, u) x 4 faces x EW
+  static constexpr int CHP = CH % 2 ? CH : CH + 1;     // padded (odd) channel stride in LDS
   // Per-wave LDS slice, in reals. A 3D array holds one real per unit pos*EW + e; a field
-  // array is 4 such planes. Face-chain arrays hold one real per unit b*CH + channel.
+  // array is 4 such planes. Face-chain arrays hold one real per unit b*CHP + channel (an
+  // odd stride, so that lanes reading one channel at consecutive b hit distinct banks).
   static constexpr int OFF_P = 0;                          // [EW][25] geometry, [EW][MP] c^2/beta!
-  static constexpr int OFF_Q = cdiv(EW * PW, 2) * 2;       // 4 planes [NP*EW] state; plane 0 later R
+  static constexpr int OFF_Q = cdiv(EW * PW, 2) * 2;       // 4 planes [NP*EW] state
   static constexpr int PLQ = EW * NP;
-  static constexpr int OFF_A = OFF_Q + 4 * PLQ;            // Y: 4 planes [NP1*EW] | F [NFP*CH], T [NFP1*CH]
+  static constexpr int OFF_A = OFF_Q + 4 * PLQ;            // Y: 4 planes [NP1*EW] | F [NFP*CHP], T [NFP1*CHP] | R [NP*EW]
   static constexpr int PLY = EW * NP1;
-  static constexpr int SA = cmax(4 * PLY + EW * (NP - NP1), CH * (NFP + NFP1));
-  static constexpr int OFF_B = OFF_A + SA;                 // chain [NP*CH] | H, H1, levels
-  static constexpr int SB = cmax(CH * NP, EW * (NH + NH1 + LEV) + 4 * EW);
+  static constexpr int SA = cmax(4 * PLY + EW * (NP - NP1), CHP * (NFP + NFP1));
+  static constexpr int OFF_B = OFF_A + SA;                 // chain [NP*CHP] | H, H1, levels
+  static constexpr int SB = cmax(CHP * NP, EW * (NH + NH1 + LEV) + 4 * EW);
   static constexpr int OFF_Z = OFF_B + SB;                 // a real that stays zero
   static constexpr int TOTAL = cdiv(OFF_Z + 2, 2) * 2;
   static constexpr int BYTES = TOTAL * (int)sizeof(real);
-  static constexpr int WPB = cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
+  // teams per workgroup: single-wave teams share a workgroup (up to 4 within 64 KiB of LDS);
+  // a multi-wave team is a workgroup of its own, synchronised by the workgroup barrier
+  static constexpr int TPB = TW > 1 ? 1 : cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
+  static constexpr int WPB = TW * TPB;
   // product positions kept in registers when they are few, computed per use otherwise
-  static constexpr bool MUL_REGS = MP * S3 <= 24;
+  static constexpr bool MUL_REGS = MP * S3 <= 40;
   // waves per SIMD that LDS allows (160 KiB per CU, 4 SIMDs); registers are budgeted for
   // the same occupancy, at most 4
-  static constexpr int LDS_WAVES = (163840 / (BYTES * WPB)) * WPB / 4;
+  static constexpr int LDS_WAVES = (163840 / (BYTES * TPB)) * WPB / 4;
   static constexpr int WAVES_EU = LDS_WAVES < 1 ? 1 : (LDS_WAVES > 4 ? 4 : LDS_WAVES);
 };
 
@@ -160,19 +180,24 @@ void stage_kernel(const StageArgs<real> a) {
   using L = StageLayout<real, N, M, EW>;
   constexpr int NP = L::NP, NP1 = L::NP1, NFP = L::NFP, NFP1 = L::NFP1, NH = L::NH, MP = L::MP;
   constexpr int S3 = L::S3, S3N = L::S3N, S2 = L::S2, SF = L::SF, SPW = L::SPW, PW = L::PW;
-  constexpr int CH = L::CH;
+  constexpr int CH = L::CH, CHP = L::CHP;
+  constexpr int TW = L::TW, TL = L::TL, TPB = L::TPB;
   constexpr int SZ = (int)sizeof(real);
   // byte offsets of the arrays inside a wave's slice
   constexpr int BP = L::OFF_P * SZ, BQ = L::OFF_Q * SZ, BA = L::OFF_A * SZ, BB = L::OFF_B * SZ;
   constexpr int BZ = L::OFF_Z * SZ;
   constexpr int PQ = L::PLQ * SZ, PY = L::PLY * SZ;  // plane strides
-  __shared__ __attribute__((aligned(16))) real smem[WPB * L::TOTAL];
+  __shared__ __attribute__((aligned(16))) real smem[TPB * L::TOTAL];
   char* const lds = reinterpret_cast<char*>(smem);
   auto at = [lds](int byteoff) -> real& { return *reinterpret_cast<real*>(lds + byteoff); };
 
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wb = wave * L::TOTAL * SZ;  // this wave's slice
+  const int lane = threadIdx.x % TL;  // lane within the team
+  const int team = __builtin_amdgcn_readfirstlane(threadIdx.x / TL);
+  const int wb = team * L::TOTAL * SZ;  // this team's slice
+  auto team_sync = [] {
+    if constexpr (TW == 1) wave_sync();
+    else __syncthreads();
+  };
   const int64_t K = a.K;
   const real* const qin = a.qin;
 
@@ -180,44 +205,34 @@ void stage_kernel(const StageArgs<real> a) {
   const int64_t ngroups = (K + EW - 1) / EW;
   const int nxcd = (gridDim.x % 8 == 0) ? 8 : 1;
   const int xcd = blockIdx.x % nxcd;
-  const int64_t waves_per_xcd = (int64_t)(gridDim.x / nxcd) * WPB;
-  const int64_t lw = (int64_t)(blockIdx.x / nxcd) * WPB + wave;
+  const int64_t waves_per_xcd = (int64_t)(gridDim.x / nxcd) * TPB;  // teams per XCD
+  const int64_t lw = (int64_t)(blockIdx.x / nxcd) * TPB + team;
   const int64_t chunk = (ngroups + nxcd - 1) / nxcd;
   const int64_t gbeg = xcd * chunk;
   const int64_t gend = gbeg + chunk < ngroups ? gbeg + chunk : ngroups;
 
-  // ---- per-lane index registers (byte offsets, computed once) -------------------------
-  // 3D slot s holds unit lane + 64 s = pos*EW + e with pos the graded position of
-  // (a1, a2, a3); up/dn are the units of alpha +- e_k (dn clamps to the unit itself when
-  // a_k = 0, where its weight is zero).
-  int pa3[S3], up3[S3][3], dn3[S3N][3];
+  // ---- per-lane index registers (computed once) -------------------------------------
+  // 3D slot s holds unit lane + 64 s = pos*EW + e, pos the graded position of (a1,a2,a3).
+  // Only the packed multi-index is kept; stencil neighbours follow from the graded order:
+  //   pos(a+e1) = pos + D(s) + a3, pos(a+e2) = pos + D(s) + a3 + 1, pos(a+e3) = pos + D(s) + s + 2
+  // with D(s) = (s+1)(s+2)/2 and s = a1+a2+a3 (and the same relations read backwards).
+  int pa3[S3];
   real fac3[S3N], facH[S3];
-  int lp[S3N][4];
-  int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? MP : 1];
+  // product positions, two 16-bit byte offsets per register
+  int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? (MP + 1) / 2 : 1];
 #pragma unroll
   for (int s = 0; s < S3; ++s) {
-    const int item = lane + 64 * s;
+    const int item = lane + TL * s;
     const int pos = item / EW, e = item - (item / EW) * EW;
     int a1 = 0, a2 = 0, a3 = 0;
     if (item < EW * NH) pos3(pos, a1, a2, a3);
     const int sa = a1 + a2 + a3;
     pa3[s] = a1 | (a2 << 8) | (a3 << 16) | (sa << 24);
-    up3[s][0] = wb + (g3(a1 + 1, a2, a3) * EW + e) * SZ;
-    up3[s][1] = wb + (g3(a1, a2 + 1, a3) * EW + e) * SZ;
-    up3[s][2] = wb + (g3(a1, a2, a3 + 1) * EW + e) * SZ;
     const int a0N = N - sa, a0H = N + M - sa;
     facH[s] = real(double(fact(a0H) * fact(a1) * fact(a2) * fact(a3)) / double(binom(N + M, N)));
     if (s < S3N) {
       const int sN = s < S3N ? s : 0;
-      dn3[sN][0] = wb + (a1 > 0 ? g3(a1 - 1, a2, a3) * EW + e : item) * SZ;
-      dn3[sN][1] = wb + (a2 > 0 ? g3(a1, a2 - 1, a3) * EW + e : item) * SZ;
-      dn3[sN][2] = wb + (a3 > 0 ? g3(a1, a2, a3 - 1) * EW + e : item) * SZ;
       fac3[sN] = (a0N >= 0) ? real(1) / real(fact(a0N) * fact(a1) * fact(a2) * fact(a3)) : real(0);
-      const int af[4] = {a0N, a1, a2, a3};
-      const int b1f[4] = {a2, a2, a1, a1}, b2f[4] = {a3, a3, a3, a2};
-#pragma unroll
-      for (int f = 0; f < 4; ++f)
-        lp[sN][f] = wb + ((af[f] >= 0 ? (chain_off(N, af[f]) + g2(b1f[f], b2f[f])) : 0) * CH + f * EW + e) * SZ;
     }
     if constexpr (L::MUL_REGS) {
       int b = 0;  // beta in the graded coefficient order of c^2
@@ -229,30 +244,28 @@ void stage_kernel(const StageArgs<real> a) {
           for (int b2 = 0; b2 <= sb - b3; ++b2) {
             const int b1 = sb - b2 - b3, b0 = M - sb;
             const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0H >= b0;
-            mpos[s][b] = wb + (ok ? BQ + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
+            const int off = wb + (ok ? BA + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
+            if (b % 2 == 0) mpos[s][b / 2] = off;
+            else mpos[s][b / 2] |= off << 16;
             ++b;
           }
     }
   }
-  // face-chain slot t holds unit b*CH + ch with b the graded face position of (b1, b2)
-  int pb2[S2], up2[S2][2], dn2[S2][2];
+  // face-chain slot t holds item b*CH + ch (b the graded face position of (b1, b2)),
+  // stored at unit b*CHP + ch; neighbours: pos(b+e1) = pos + t + 1, pos(b+e2) = pos + t + 2
+  int pb2[S2];
 #pragma unroll
   for (int t = 0; t < S2; ++t) {
-    const int item = lane + 64 * t;
-    const int b = item / CH, ch = item - (item / CH) * CH;
+    const int item = lane + TL * t;
     int b1 = 0, b2 = 0;
-    if (item < CH * NFP) pos2(b, b1, b2);
+    if (item < CH * NFP) pos2(item / CH, b1, b2);
     pb2[t] = b1 | (b2 << 8) | ((b1 + b2) << 16);
-    up2[t][0] = wb + (g2(b1 + 1, b2) * CH + ch) * SZ;
-    up2[t][1] = wb + (g2(b1, b2 + 1) * CH + ch) * SZ;
-    dn2[t][0] = wb + (b1 > 0 ? g2(b1 - 1, b2) * CH + ch : item) * SZ;
-    dn2[t][1] = wb + (b2 > 0 ? g2(b1, b2 - 1) * CH + ch : item) * SZ;
   }
   // flux slot u holds face coefficient m of face f of element e (unit m*4EW + f*EW + e)
   int fown[SF], fnb[SF], ffe[SF];
 #pragma unroll
   for (int u = 0; u < SF; ++u) {
-    const int item = lane + 64 * u;
+    const int item = lane + TL * u;
     const int m = item / (4 * EW), fe = item - (item / (4 * EW)) * (4 * EW);
     const int f = fe / EW, e = fe - (fe / EW) * EW;
     int b1 = 0, b2 = 0;
@@ -268,7 +281,7 @@ void stage_kernel(const StageArgs<real> a) {
   real pscale[SPW];
 #pragma unroll
   for (int r = 0; r < SPW; ++r) {
-    const int i = lane + 64 * r;
+    const int i = lane + TL * r;
     pscale[r] = real(1);
     if (i >= 25 * EW && i < PW * EW) {
       const int bpos = (i - 25 * EW) % MP;
@@ -278,9 +291,49 @@ void stage_kernel(const StageArgs<real> a) {
     }
   }
 
+  // Per-phase neighbour offsets (bytes, this wave's slice), derived from the packed indices.
+  struct N3 {
+    int self, up[3], dn[3], a1, a2, a3, sa;
+  };
+  auto nb3 = [&](int s) -> N3 {
+    const int p = opq(pa3[s]);
+    N3 r;
+    r.a1 = p & 255;
+    r.a2 = (p >> 8) & 255;
+    r.a3 = (p >> 16) & 255;
+    r.sa = p >> 24;
+    r.self = wb + (lane + TL * s) * SZ;
+    const int du = ((r.sa + 1) * (r.sa + 2) >> 1) * EW * SZ;  // D(s)
+    const int dd = ((r.sa * (r.sa + 1)) >> 1) * EW * SZ;      // D(s-1)
+    r.up[0] = r.self + du + r.a3 * EW * SZ;
+    r.up[1] = r.up[0] + EW * SZ;
+    r.up[2] = r.self + du + (r.sa + 2) * EW * SZ;
+    r.dn[0] = r.a1 > 0 ? r.self - dd - r.a3 * EW * SZ : r.self;
+    r.dn[1] = r.a2 > 0 ? r.self - dd - (r.a3 + 1) * EW * SZ : r.self;
+    r.dn[2] = r.a3 > 0 ? r.self - dd - (r.sa + 1) * EW * SZ : r.self;
+    return r;
+  };
+  struct N2 {
+    int self, up[2], dn[2], b1, b2, tb;
+  };
+  auto nb2 = [&](int t) -> N2 {
+    const int p = opq(pb2[t]);
+    N2 r;
+    r.b1 = p & 255;
+    r.b2 = (p >> 8) & 255;
+    r.tb = p >> 16;
+    const int item = lane + TL * t;
+    r.self = wb + (item + item / CH) * SZ;  // unit b*CHP + ch with CHP = CH + 1
+    r.up[0] = r.self + (r.tb + 1) * CHP * SZ;
+    r.up[1] = r.self + (r.tb + 2) * CHP * SZ;
+    r.dn[0] = r.b1 > 0 ? r.self - r.tb * CHP * SZ : r.self;
+    r.dn[1] = r.b2 > 0 ? r.self - (r.tb + 1) * CHP * SZ : r.self;
+    return r;
+  };
+
   // zero this wave's LDS slice once (stale reads are weighted by zero and must be finite)
-  for (int i = lane; i < L::TOTAL; i += 64) at(wb + i * SZ) = real(0);
-  wave_sync();
+  for (int i = lane; i < L::TOTAL; i += TL) at(wb + i * SZ) = real(0);
+  team_sync();
 
   // ---- prefetch of the next element group ------------------------------------------------
   real qn[4][S3N], pn[SPW];
@@ -289,7 +342,7 @@ void stage_kernel(const StageArgs<real> a) {
     const int64_t k0 = g * EW;
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
+      const int item = lane + TL * s;
       const int e = item - (item / EW) * EW, pos = item / EW;
       const bool ok = item < EW * NP && k0 + e < K;
 #pragma unroll
@@ -297,7 +350,7 @@ void stage_kernel(const StageArgs<real> a) {
     }
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
-      const int i = lane + 64 * r;
+      const int i = lane + TL * r;
       real v = real(0);
       if (i < 25 * EW) {
         if (k0 + i / 25 < K) v = a.geo[k0 * kGeoStride + i];
@@ -309,7 +362,7 @@ void stage_kernel(const StageArgs<real> a) {
     }
 #pragma unroll
     for (int u = 0; u < SF; ++u) {
-      const int item = lane + 64 * u;
+      const int item = lane + TL * u;
       const int fe = ffe[u] & 0xFFFF, f = fe / EW, e = fe - (fe / EW) * EW;
       cn[u] = (item < 4 * EW * NFP && k0 + e < K) ? a.conn[(k0 + e) * 4 + f] : -1;
     }
@@ -320,35 +373,26 @@ void stage_kernel(const StageArgs<real> a) {
 
   for (; g < gend; g += waves_per_xcd) {
     const int64_t k0 = g * EW;
+    if constexpr (L::MUL_REGS) {  // keep unpacking of the product positions inside the loop
+#pragma unroll
+      for (int s = 0; s < S3; ++s)
+#pragma unroll
+        for (int b = 0; b < (MP + 1) / 2; ++b) asm volatile("" : "+v"(mpos[s][b]));
+    }
     // ---- stage this group's scalars and state into LDS --------------------------------
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
-      const int i = lane + 64 * r;
+      const int i = lane + TL * r;
       if (i < PW * EW) at(wb + BP + i * SZ) = pn[r] * pscale[r];
     }
-    real q[4][S3N];
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
+      const int item = lane + TL * s;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        q[f][s] = qn[f][s];
-        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = q[f][s];
-      }
+      for (int f = 0; f < 4; ++f)
+        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = qn[f][s];
     }
-    // ---- issue this group's RK register and neighbour traces, then the next prefetch ----
-    real rs[4][S3N];
-#pragma unroll
-    for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
-      const int e = item - (item / EW) * EW, pos = item / EW;
-      const bool ok = item < EW * NP && k0 + e < K;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        if constexpr (UPDATE) rs[f][s] = ok ? a.res[((size_t)f * K + k0 + e) * NP + pos] : real(0);
-        else rs[f][s] = real(0);
-      }
-    }
+    // ---- issue this group's neighbour traces, then the next prefetch ---------------------
     real nb[4][SF];
     int cur_conn[SF];
 #pragma unroll
@@ -368,25 +412,26 @@ void stage_kernel(const StageArgs<real> a) {
     }
     const int64_t gnext = g + waves_per_xcd;
     if (gnext < gend) prefetch(gnext);
-    wave_sync();
+    team_sync();
 
     // ---- volume: reference derivatives at degree N-1 -----------------------------------
     // Y planes: -dp/dx, -dp/dy, -dp/dz, -div u at degree N-1 (times N/2)
     constexpr real half_n = real(N) / real(2);
 #pragma unroll
     for (int s = 0; s < S3; ++s) {
-      const int item = lane + 64 * s;
-      if (s * 64 < EW * NP1 && item < EW * NP1) {
+      const int item = lane + TL * s;
+      if (s * TL < EW * NP1 && item < EW * NP1) {
         const int e = item - (item / EW) * EW;
         const int gm = wb + BP + e * 25 * SZ;
-        const int self = wb + item * SZ;
+        const N3 x = nb3(s);
+        const int self = x.self;
         real v0[4], v1[4], v2[4], v3[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           v0[f] = at(self + BQ + f * PQ);
-          v1[f] = at(up3[s][0] + BQ + f * PQ);
-          v2[f] = at(up3[s][1] + BQ + f * PQ);
-          v3[f] = at(up3[s][2] + BQ + f * PQ);
+          v1[f] = at(x.up[0] + BQ + f * PQ);
+          v2[f] = at(x.up[1] + BQ + f * PQ);
+          v3[f] = at(x.up[2] + BQ + f * PQ);
         }
         real dv = 0;
         real gr[3];
@@ -402,35 +447,36 @@ void stage_kernel(const StageArgs<real> a) {
         at(self + BA + 3 * PY) = -half_n * dv;
       }
     }
-    wave_sync();
+    team_sync();
     // elevate to degree N: acc[0] = -div u, acc[1 + i] = -d p / d x_i
     real acc[4][S3N] = {};
     constexpr real inv_n = real(1) / real(N);
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
+      const int item = lane + TL * s;
       if (item >= EW * NP) continue;
-      const int self = wb + item * SZ;
-      const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
-      const real w0 = real(N - sa) * inv_n, w1 = real(a1) * inv_n, w2 = real(a2) * inv_n, w3 = real(a3) * inv_n;
+      const N3 x = nb3(s);
+      const int self = x.self;
+      const real w0 = real(N - x.sa) * inv_n, w1 = real(x.a1) * inv_n, w2 = real(x.a2) * inv_n,
+                 w3 = real(x.a3) * inv_n;
       real t[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        t[c] = w0 * at(self + BA + c * PY) + w1 * at(dn3[s][0] + BA + c * PY) + w2 * at(dn3[s][1] + BA + c * PY) +
-               w3 * at(dn3[s][2] + BA + c * PY);
+        t[c] = w0 * at(self + BA + c * PY) + w1 * at(x.dn[0] + BA + c * PY) + w2 * at(x.dn[1] + BA + c * PY) +
+               w3 * at(x.dn[2] + BA + c * PY);
       acc[0][s] = t[3];
       acc[1][s] = t[0];
       acc[2][s] = t[1];
       acc[3][s] = t[2];
     }
-    wave_sync();
+    team_sync();
 
     // ---- surface: penalty fluxes per face coefficient ------------------------------------
-    // F [NFP*CH] at BA, channel (type*4 + f)*EW + e; T [NFP1*CH] right after it
-    constexpr int BF = BA, BT = BA + CH * NFP * SZ;
+    // F [NFP*CHP] at BA, channel (type*4 + f)*EW + e; T [NFP1*CHP] right after it
+    constexpr int BF = BA, BT = BA + CHP * NFP * SZ;
 #pragma unroll
     for (int u = 0; u < SF; ++u) {
-      const int item = lane + 64 * u;
+      const int item = lane + TL * u;
       if (item < 4 * EW * NFP) {
         const int fe = ffe[u] & 0xFFFF, m = ffe[u] >> 16;
         const int f = fe / EW, e = fe - (fe / EW) * EW;
@@ -458,72 +504,90 @@ void stage_kernel(const StageArgs<real> a) {
         }
         const real jp = pp - pm;
         const real jun = (up - um) * nx + (vp - vm) * ny + (wp - wm) * nz;
-        const int dst = wb + BF + (m * CH + fe) * SZ;
+        const int dst = wb + BF + (m * CHP + fe) * SZ;
         at(dst) = real(0.5) * (a.tau_p * jp - jun);
         at(dst + 4 * EW * SZ) = real(0.5) * (a.tau_u * jun - jp);
       }
     }
-    wave_sync();
+    // the RK register of this group: issued now, consumed by the update at the end
+    real rs[4][S3N];
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + TL * s;
+      const int e = item - (item / EW) * EW, pos = item / EW;
+      const bool ok = item < EW * NP && k0 + e < K;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if constexpr (UPDATE) rs[f][s] = ok ? a.res[((size_t)f * K + k0 + e) * NP + pos] : real(0);
+        else rs[f][s] = real(0);
+      }
+    }
+    team_sync();
 
     // ---- lift: L_0 on each face flux, then the layer chain (levels pre-scaled by l_i) -----
 #pragma unroll
     for (int t = 0; t < S2; ++t) {  // T = (E^N_{N-1})^T F
-      const int item = lane + 64 * t;
-      if (t * 64 < CH * NFP1 && item < CH * NFP1) {
-        const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
-        const int self = wb + item * SZ;
-        at(self + BT) = inv_n * (real(N - tb) * at(self + BF) + real(b1 + 1) * at(up2[t][0] + BF) +
-                                 real(b2 + 1) * at(up2[t][1] + BF));
+      const int item = lane + TL * t;
+      if (t * TL < CH * NFP1 && item < CH * NFP1) {
+        const N2 x = nb2(t);
+        at(x.self + BT) = inv_n * (real(N - x.tb) * at(x.self + BF) + real(x.b1 + 1) * at(x.up[0] + BF) +
+                                   real(x.b2 + 1) * at(x.up[1] + BF));
       }
     }
-    wave_sync();
-    constexpr int BC = BB;  // chain [NP*CH], level i at chain_off(N, i)*CH
+    team_sync();
+    constexpr int BC = BB;  // chain [NP*CHP], level i at chain_off(N, i)*CHP
     {
       constexpr real l0a = real(2 * N + 3) / real(2);
       constexpr real l0b = real(N * N) / real(2) / real(N);
 #pragma unroll
       for (int t = 0; t < S2; ++t) {  // level 0 = L_0 F = (2N+3)/2 F + N^2/2 E T
-        const int item = lane + 64 * t;
+        const int item = lane + TL * t;
         if (item < CH * NFP) {
-          const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
-          const int self = wb + item * SZ;
-          const real et = real(N - tb) * at(self + BT) + real(b1) * at(dn2[t][0] + BT) + real(b2) * at(dn2[t][1] + BT);
-          at(self + BC) = l0a * at(self + BF) + l0b * et;
+          const N2 x = nb2(t);
+          const real et =
+              real(N - x.tb) * at(x.self + BT) + real(x.b1) * at(x.dn[0] + BT) + real(x.b2) * at(x.dn[1] + BT);
+          at(x.self + BC) = l0a * at(x.self + BF) + l0b * et;
         }
       }
     }
-    wave_sync();
+    team_sync();
 #pragma unroll
     for (int i = 1; i <= N; ++i) {
       const int n = N - i + 1;  // level i-1 has degree n
       const real sc = real(lift_ell(N, i) / lift_ell(N, i - 1)) / real(n);
       const int cnt = CH * dim2(n - 1);
-      const int src = BC + chain_off(N, i - 1) * CH * SZ, dst = BC + chain_off(N, i) * CH * SZ;
+      const int src = BC + chain_off(N, i - 1) * CHP * SZ, dst = BC + chain_off(N, i) * CHP * SZ;
 #pragma unroll
       for (int t = 0; t < S2; ++t) {
-        const int item = lane + 64 * t;
-        if (t * 64 < cnt && item < cnt) {
-          const int b1 = pb2[t] & 255, b2 = (pb2[t] >> 8) & 255, tb = pb2[t] >> 16;
-          const int self = wb + item * SZ;
-          at(self + dst) = sc * (real(n - tb) * at(self + src) + real(b1 + 1) * at(up2[t][0] + src) +
-                                 real(b2 + 1) * at(up2[t][1] + src));
+        const int item = lane + TL * t;
+        if (t * TL < cnt && item < cnt) {
+          const N2 x = nb2(t);
+          at(x.self + dst) = sc * (real(n - x.tb) * at(x.self + src) + real(x.b1 + 1) * at(x.up[0] + src) +
+                                   real(x.b2 + 1) * at(x.up[1] + src));
         }
       }
-      wave_sync();
+      team_sync();
     }
     // gather the four face lifts into every coefficient
-    constexpr int BR = BQ;  // r_p / alpha! (degree N), in the first state plane
+    constexpr int BR = BA;  // r_p / alpha! (degree N); F and T are dead once level 0 is formed
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
+      const int item = lane + TL * s;
       if (item < EW * NP) {
         const int e = item - (item / EW) * EW;
+        const int p = opq(pa3[s]);
+        const int a1 = p & 255, a2 = (p >> 8) & 255, a3 = (p >> 16) & 255, sa = p >> 24;
+        const int af[4] = {N - sa, a1, a2, a3};
+        const int b1f[4] = {a2, a2, a1, a1}, b2f[4] = {a3, a3, a3, a2};
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
+          // level alpha_f of face f's chain starts at dimp(N) - dimp(N - alpha_f)
+          const int rem = N - af[f];
+          const int lpf = wb + ((NP - (rem + 1) * (rem + 2) * (rem + 3) / 6 + g2(b1f[f], b2f[f])) * CHP + f * EW + e) * SZ;
           const real sc = at(gf);
-          const real lpv = at(lp[s][f] + BC);
-          const real luv = at(lp[s][f] + BC + 4 * EW * SZ) * sc;
+          const real lpv = at(lpf + BC);
+          const real luv = at(lpf + BC + 4 * EW * SZ) * sc;
           acc[0][s] += sc * lpv;
           acc[1][s] += at(gf + SZ) * luv;
           acc[2][s] += at(gf + 2 * SZ) * luv;
@@ -539,21 +603,25 @@ void stage_kernel(const StageArgs<real> a) {
 
     // ---- WADG: product with c^2_M, M reductions, telescoped projection -----------------
     if constexpr (M > 0) {
-      wave_sync();
+      team_sync();
       constexpr int NH1 = L::NH1;
       constexpr int BH = BB, BH1 = BB + EW * NH * SZ, BL = BH1 + EW * NH1 * SZ;
 #pragma unroll
       for (int s = 0; s < S3; ++s) {
-        const int item = lane + 64 * s;
+        const int item = lane + TL * s;
         if (item < EW * NH) {
           const int e = item - (item / EW) * EW;
           const int c2s = wb + BP + (25 * EW + e * MP) * SZ;
           real h = 0;
           if constexpr (L::MUL_REGS) {
 #pragma unroll
-            for (int b = 0; b < MP; ++b) h += at(mpos[s][b]) * at(c2s + b * SZ);
+            for (int b = 0; b < MP; ++b) {
+              const int off = (b % 2 == 0) ? (mpos[s][b / 2] & 0xFFFF) : ((unsigned)mpos[s][b / 2] >> 16);
+              h += at(off) * at(c2s + b * SZ);
+            }
           } else {
-            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
+            const int pp = opq(pa3[s]);
+            const int a1 = pp & 255, a2 = (pp >> 8) & 255, a3 = (pp >> 16) & 255, sa = pp >> 24;
             const int a0 = N + M - sa;
             int b = 0;  // beta in the graded coefficient order of c^2
 #pragma unroll
@@ -572,7 +640,7 @@ void stage_kernel(const StageArgs<real> a) {
           at(wb + BH + item * SZ) = h * facH[s];
         }
       }
-      wave_sync();
+      team_sync();
       // M reductions: degree N+M -> N; the last one writes level 0 of the telescoping
 #pragma unroll
       for (int n = N + M; n > N; --n) {
@@ -582,15 +650,14 @@ void stage_kernel(const StageArgs<real> a) {
         const int cnt = EW * dimp(n - 1);
 #pragma unroll
         for (int s = 0; s < S3; ++s) {
-          const int item = lane + 64 * s;
-          if (s * 64 < cnt && item < cnt) {
-            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
-            const int self = wb + item * SZ;
-            at(self + dst) = inv * (real(n - sa) * at(self + src) + real(a1 + 1) * at(up3[s][0] + src) +
-                                    real(a2 + 1) * at(up3[s][1] + src) + real(a3 + 1) * at(up3[s][2] + src));
+          const int item = lane + TL * s;
+          if (s * TL < cnt && item < cnt) {
+            const N3 x = nb3(s);
+            at(x.self + dst) = inv * (real(n - x.sa) * at(x.self + src) + real(x.a1 + 1) * at(x.up[0] + src) +
+                                      real(x.a2 + 1) * at(x.up[1] + src) + real(x.a3 + 1) * at(x.up[2] + src));
           }
         }
-        wave_sync();
+        team_sync();
       }
       // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1
 #pragma unroll
@@ -601,19 +668,18 @@ void stage_kernel(const StageArgs<real> a) {
         const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
 #pragma unroll
         for (int s = 0; s < S3N; ++s) {
-          const int item = lane + 64 * s;
-          if (s * 64 < cnt && item < cnt) {
-            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
-            const int self = wb + item * SZ;
-            at(self + dst) = inv * (real(n - sa) * at(self + src) + real(a1 + 1) * at(up3[s][0] + src) +
-                                    real(a2 + 1) * at(up3[s][1] + src) + real(a3 + 1) * at(up3[s][2] + src));
+          const int item = lane + TL * s;
+          if (s * TL < cnt && item < cnt) {
+            const N3 x = nb3(s);
+            at(x.self + dst) = inv * (real(n - x.sa) * at(x.self + src) + real(x.a1 + 1) * at(x.up[0] + src) +
+                                      real(x.a2 + 1) * at(x.up[1] + src) + real(x.a3 + 1) * at(x.up[2] + src));
           }
         }
-        wave_sync();
+        team_sync();
       }
       // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}
       if (lane < EW) at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) *= a.cj[N];
-      wave_sync();
+      team_sync();
 #pragma unroll
       for (int j = N - 1; j >= 0; --j) {
         const int n = N - j;
@@ -623,20 +689,19 @@ void stage_kernel(const StageArgs<real> a) {
         const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
 #pragma unroll
         for (int s = 0; s < S3N; ++s) {
-          const int item = lane + 64 * s;
-          if (s * 64 < cnt && item < cnt) {
-            const int a1 = pa3[s] & 255, a2 = (pa3[s] >> 8) & 255, a3 = (pa3[s] >> 16) & 255, sa = pa3[s] >> 24;
-            const int self = wb + item * SZ;
-            const real el = real(n - sa) * at(self + hi) + real(a1) * at(dn3[s][0] + hi) +
-                            real(a2) * at(dn3[s][1] + hi) + real(a3) * at(dn3[s][2] + hi);
-            at(self + lo) = cj * at(self + lo) + inv * el;
+          const int item = lane + TL * s;
+          if (s * TL < cnt && item < cnt) {
+            const N3 x = nb3(s);
+            const real el = real(n - x.sa) * at(x.self + hi) + real(x.a1) * at(x.dn[0] + hi) +
+                            real(x.a2) * at(x.dn[1] + hi) + real(x.a3) * at(x.dn[2] + hi);
+            at(x.self + lo) = cj * at(x.self + lo) + inv * el;
           }
         }
-        wave_sync();
+        team_sync();
       }
 #pragma unroll
       for (int s = 0; s < S3N; ++s) {
-        const int item = lane + 64 * s;
+        const int item = lane + TL * s;
         if (item < EW * NP) acc[0][s] = at(wb + BL + item * SZ);
       }
     }
@@ -644,7 +709,7 @@ void stage_kernel(const StageArgs<real> a) {
     // ---- write: rhs, or the low-storage RK stage --------------------------------------------
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
-      const int item = lane + 64 * s;
+      const int item = lane + TL * s;
       const int e = item - (item / EW) * EW, pos = item / EW;
       if (item < EW * NP && k0 + e < K) {
 #pragma unroll
@@ -653,14 +718,14 @@ void stage_kernel(const StageArgs<real> a) {
           if constexpr (UPDATE) {
             const real r = a.rk_a * rs[f][s] + a.dt * acc[f][s];
             a.res[gi] = r;
-            a.qout[gi] = q[f][s] + a.rk_b * r;
+            a.qout[gi] = at(wb + BQ + f * PQ + item * SZ) + a.rk_b * r;
           } else {
             a.qout[gi] = acc[f][s];
           }
         }
       }
     }
-    wave_sync();  // the next group overwrites this wave's LDS slice
+    team_sync();  // the next group overwrites this team's LDS slice
   }
 }
 
@@ -690,7 +755,7 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
     grid = (grid / 8) * 8 > 0 ? (grid / 8) * 8 : grid;
   }
   const int64_t groups = (a.K + EW - 1) / EW;
-  const int64_t need = (groups + WPB - 1) / WPB;
+  const int64_t need = (groups + L::TPB - 1) / L::TPB;  // one team per element group
   int blocks = grid;
   if (need < blocks) blocks = (int)(need >= 8 ? (need / 8) * 8 : need);
   if (blocks <= 0) return 0;
