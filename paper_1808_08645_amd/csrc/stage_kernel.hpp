@@ -749,7 +749,8 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
       fprintf(stderr, "bbwadg: N=%d M=%d sizeof(real)=%d WPB=%d occupancy blocks/CU=%d numRegs=%d lds=%zu\n", N, M,
               (int)sizeof(real), WPB, per_cu, attr.numRegs, (size_t)attr.sharedSizeBytes);
     }
-    if (const char* env = getenv("BBWADG_BLOCKS_PER_CU")) per_cu = atoi(env);  // tuning override
+    const char* env = getenv("BBWADG_BLOCKS_PER_CU");  // tuning override
+    if (env && *env) per_cu = atoi(env);
     if (per_cu <= 0) per_cu = 1;
     grid = ncu * per_cu;
     grid = (grid / 8) * 8 > 0 ? (grid / 8) * 8 : grid;

@@ -266,3 +266,83 @@ def test_full_size_step_parity_on_sampled_elements(bb):
     # fields that are exactly zero at the sampled elements are compared absolutely
     err = np.where(den > 1e-200, np.sqrt(num / den), np.sqrt(num))
     assert np.all(err < FP64_TOL), err
+
+
+@pytest.mark.parametrize("N", [4, 6, 7, 8, 9])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_layered_medium_step_parity(bb, N, dtype):
+    """Three-layer medium (c^2 in {1, 2, 4}, tilted interfaces cutting through elements),
+    M = N // 2, Gaussian pulse, 3 LSRK4 steps; both sides project c^2 and the start state
+    with their own code."""
+    import torch
+    from workloads import c2_three_layer
+    print(f"[layers] N={N} {dtype}", flush=True)
+    M = N // 2
+    xyz, etov = kuhn_cube_mesh(3)
+    medium = c2_three_layer(1)
+    pulse = lambda x, y, z: ic_gaussian_pulse(x, y, z, width=0.2)  # noqa: E731
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    s.project_c2(medium)
+    q = s.to_device(s.initial_state([pulse, zero, zero, zero]))
+    res = torch.zeros_like(q)
+    dt = 5e-4
+    s.step(q, res, dt, 3)
+    torch.cuda.synchronize()
+    o = Oracle(xyz, etov, N, M)
+    o.set_c2_function(medium, project=True)
+    Q0 = o.project_initial([pulse, zero, zero, zero])
+    Q, _ = o.step(Q0, np.zeros_like(Q0), dt, 3)
+    err = _compare(o, q, Q)
+    tol = FP64_TOL if dtype == "f64" else fp32_tol(N)
+    assert np.all(err < tol), err
+
+
+def test_device_error_paths(bb):
+    import torch
+    xyz, etov = kuhn_cube_mesh(1)
+    s = bb.Solver(xyz, etov, 3, 1)
+    q = s.empty_state()
+    with pytest.raises(bb.BBWADGError) as ei:  # c^2 not set
+        s.rhs(q)
+    assert ei.value.code == -3
+    s.set_c2(np.ones((s.K, s.Mp)))
+    lib = bb.load_library()
+    import ctypes as C
+    p = C.c_void_p(q.data_ptr())
+    assert lib.bbwadg_rhs(s._ctx, p, p, 0.0, None) == -1  # q and rhs overlap
+    assert lib.bbwadg_step(s._ctx, p, C.c_void_p(s.empty_state().data_ptr()), 0.0, 1e-3, -1, None) == -1
+    with pytest.raises(ValueError):
+        s.rhs(torch.zeros((4, s.K, s.Np + 1), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        s.rhs(torch.zeros((4, s.K, s.Np), dtype=torch.float32, device="cuda"))
+    # zero steps leave the state unchanged
+    q0 = s.to_device(random_state(3, s.K, s.Np))
+    q1 = q0.clone()
+    s.step(q1, torch.zeros_like(q1), 1e-3, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(q0, q1)
+
+
+def test_full_size_fp32_tracks_fp64(bb):
+    """196,608 tets, N=5, M=2: 20 FP32 steps stay within 1e-5 (relative L^2 per field) of
+    the FP64 path from the same start (the FP64 path itself is checked against the oracle)."""
+    import torch
+    xyz, etov = kuhn_cube_mesh(32)
+    bumps = c2_gaussian_bumps(0)
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    out = {}
+    for dtype in ("f64", "f32"):
+        s = bb.Solver(xyz, etov, 5, 2, dtype=dtype)
+        s.project_c2(bumps)
+        if dtype == "f64":
+            q0 = s.initial_state([ic_gaussian_pulse, zero, zero, zero])
+        q = s.to_device(q0)
+        res = torch.zeros_like(q)
+        s.step(q, res, 2.5e-4, 20)
+        torch.cuda.synchronize()
+        out[dtype] = (s, q.double())
+    s64, a = out["f64"]
+    b = out["f32"][1]
+    rel = np.sqrt(s64.l2norm2((b - a).contiguous()) / s64.l2norm2(a))
+    assert np.all(rel < 1e-5), rel
