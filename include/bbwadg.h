@@ -170,6 +170,41 @@ int bbwadg_suggest_dt(const bbwadg_ctx* ctx, double cfl, double* dt);
  * out: host double[4]. Synchronises `stream`. */
 int bbwadg_l2norm2(bbwadg_ctx* ctx, const void* q, double out[4], void* stream);
 
+/* ---- FP64 quadrature reductions (L^2 errors as in the convergence study of paper
+ * Section 6.1; the acoustic energy of eq. (awave), in which WADG is stable, Section 3) ----
+ * Both evaluate the device state q [4][K][Np] at the points of the degree-N projection rule
+ * (the points bbwadg_projection_points(ctx, N, ...) returns, in that order; nq = (N+3)^3
+ * per element; exact for polynomials of degree 2N+5) and accumulate in FP64 whatever the
+ * context's dtype. They cover elements [k0, k1), so a large mesh can be reduced in pieces
+ * whose results add; k0 == k1 gives zeros. The host sums per-block partials in a fixed
+ * order (deterministic). Synchronise `stream`. EINVAL on a bad range or NULL pointer. */
+
+/* out[f] = sum_{k0<=k<k1} J_k sum_q w_q (q_f(x_q) - exact[f][k-k0][q])^2, the squared L^2
+ * error of field f against a reference solution that the caller sampled at the rule points.
+ * exact: device FP64 [4][k1-k0][nq], caller-owned. */
+int bbwadg_l2error2(bbwadg_ctx* ctx, const void* q, int64_t k0, int64_t k1, const double* exact,
+                    double out[4], void* stream);
+
+/* Acoustic energy (1/2) int (p^2 / c^2_M + |u|^2) over elements [k0, k1), returned per term:
+ * out[0] = the p^2/c^2_M term, out[1..3] = the u, v, w terms (the energy is their sum), with
+ * the context's stored c^2_M (EC2 if none). Where c^2_M is constant on an element this equals
+ * the weight-adjusted energy (1/2)(p^T M M_{c^2}^{-1} M p + u^T M u) of the semi-discrete
+ * scheme; otherwise it bounds that quantity from above (Cauchy-Schwarz). */
+int bbwadg_energy(bbwadg_ctx* ctx, const void* q, int64_t k0, int64_t k1, double out[4], void* stream);
+
+/* Project fn(x, y, z, user) onto P^N per element (the degree-N projection rule, FP64 on the
+ * host, as in bbwadg_project_samples) and write the coefficients, converted to dtype, as field
+ * `field` (0 = p, 1..3 = u, v, w) of the device state q_out [4][K][Np]; the other fields are
+ * untouched. Initial conditions, paper Section 6. EINVAL for a non-finite sample or a field
+ * outside 0..3. Synchronises `stream`. */
+int bbwadg_project_fn(bbwadg_ctx* ctx, double (*fn)(double x, double y, double z, void* user),
+                      void* user, int32_t field, void* q_out, void* stream);
+
+/* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
+ * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
+ * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */
+int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3);
+
 /* c_j of the telescoped projection P^{N+M}_N = sum_j c_j E^N_{N-j}(E^N_{N-j})^T
  * (E^{N+M}_N)^T (paper Theorem 5.1, Table 1), host double[N+1]. With M < 0 returns the
  * coefficients of the inverse mass matrix representation (paper Theorem 5.2, Table 2).

@@ -121,18 +121,29 @@ class Oracle:
     # ----------------------------------------------------------------- c^2 setup
     def set_c2_bernstein(self, coef):
         """c^2_M given as per-element Bernstein coefficients [K, M_p] of degree M."""
-        coef = np.asarray(coef, dtype=np.float64)
-        B = bernstein_tet(self.M, self.rq, self.sq, self.tq)
-        self.c2q = coef @ B.T
+        coef = np.asarray(coef, dtype=np.float64).copy()
+        self._c2_ref = lambda r, s, t: coef @ bernstein_tet(self.M, r, s, t).T
+        self.c2q = self._c2_ref(self.rq, self.sq, self.tq)
 
     def set_c2_function(self, fn, project: bool = True, nproj: int | None = None):
         """c^2 from a function: its per-element L^2 projection onto P^M (the fast method's
         input, paper Section 5) or, with ``project=False``, its point values (plain WADG)."""
         if not project:
-            X = self.mesh.map_points(self.rq, self.sq, self.tq)
-            self.c2q = fn(X[..., 0], X[..., 1], X[..., 2])
-            return
-        self.c2q = self.project_to_quad(fn, self.M, nproj)
+            def at(r, s, t):
+                X = self.mesh.map_points(r, s, t)
+                return np.broadcast_to(fn(X[..., 0], X[..., 1], X[..., 2]), X.shape[:-1])
+        else:
+            modal = self.project_modal(fn, self.M, nproj)
+            def at(r, s, t):
+                return modal @ dubiner_tet(self.M, r, s, t).T
+        self._c2_ref = at
+        self.c2q = at(self.rq, self.sq, self.tq)
+
+    def c2_at(self, r, s, t):
+        """c^2 as set, at reference points (r, s, t) of every element: [K, npts]."""
+        if self.c2q is None:
+            raise RuntimeError("c^2 not set")
+        return self._c2_ref(np.atleast_1d(r), np.atleast_1d(s), np.atleast_1d(t))
 
     def project_modal(self, fn, deg: int, nproj: int | None = None):
         """Per-element L^2 projection of fn onto P^deg, as orthonormal-basis coefficients.
@@ -278,6 +289,34 @@ class Oracle:
                 un = np.einsum("ikq,ki->kq", own[1:, bm], n[bm])
                 tot += np.sum(np.sum(self.tau_u * un ** 2 * wts[bm], axis=1))
         return -tot
+
+    def error_rule(self, nproj: int | None = None):
+        """The rule of the error and energy integrals: collapsed Gauss-Jacobi with N+3 points
+        per direction (exact to degree 2N+5), the rule of the degree-N projection. The paper
+        does not fix the rule of its L^2 errors; this reading is shared with the library."""
+        return tet_rule(self.N + 3 if nproj is None else nproj)
+
+    def l2_error_sq(self, Q, fns, nproj: int | None = None):
+        """Per-field sum_k J_k int_ref (q_h - f)^2 by the error rule, for a state Q [4, K, Np]
+        (orthonormal coefficients) and four vectorised functions f(x, y, z)."""
+        r, s, t, w = self.error_rule(nproj)
+        vals = np.asarray(Q, dtype=np.float64) @ dubiner_tet(self.N, r, s, t).T  # [4, K, nq]
+        X = self.mesh.map_points(r, s, t)
+        ex = np.stack([np.broadcast_to(f(X[..., 0], X[..., 1], X[..., 2]), vals.shape[1:]) for f in fns])
+        wJ = self.mesh.J[:, None] * w[None, :]
+        return np.sum((vals - ex) ** 2 * wJ[None], axis=(1, 2))
+
+    def energy_terms(self, Q, nproj: int | None = None):
+        """(1/2) sum_k J_k int_ref of p^2 / c^2 and of u_i^2, by the error rule: [4] (the
+        acoustic energy of eq. (awave) is their sum)."""
+        r, s, t, w = self.error_rule(nproj)
+        vals = np.asarray(Q, dtype=np.float64) @ dubiner_tet(self.N, r, s, t).T
+        c2 = self.c2_at(r, s, t)
+        wJ = 0.5 * self.mesh.J[:, None] * w[None, :]
+        out = np.empty(4)
+        out[0] = np.sum(vals[0] ** 2 / c2 * wJ)
+        out[1:] = np.sum(vals[1:] ** 2 * wJ[None], axis=(1, 2))
+        return out
 
     def energy(self, Q):
         """0.5 sum_k J_k (p^T W p + u^T M u), W = M M_{c^2}^{-1} M (weight-adjusted mass).

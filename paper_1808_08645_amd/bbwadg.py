@@ -27,7 +27,8 @@ EXPORTS = (
     "bbwadg_element_vertices", "bbwadg_geometry", "bbwadg_projection_npoints",
     "bbwadg_projection_points", "bbwadg_project_samples", "bbwadg_project_c2",
     "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
-    "bbwadg_l2norm2", "bbwadg_projection_coefficients", "bbwadg_version",
+    "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
+    "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
 
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_step": (C.c_int, [vp, vp, vp, dbl, dbl, i32, vp]),
         "bbwadg_suggest_dt": (C.c_int, [vp, dbl, pd]),
         "bbwadg_l2norm2": (C.c_int, [vp, vp, pd, vp]),
+        "bbwadg_l2error2": (C.c_int, [vp, vp, i64, i64, vp, pd, vp]),
+        "bbwadg_energy": (C.c_int, [vp, vp, i64, i64, pd, vp]),
+        "bbwadg_project_fn": (C.c_int, [vp, C2_CALLBACK, vp, i32, vp, vp]),
+        "bbwadg_coef_index": (C.c_int32, [i32, i32, i32]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }
@@ -107,6 +112,15 @@ def _dptr(a):
 
 def dimp(n: int) -> int:
     return (n + 1) * (n + 2) * (n + 3) // 6
+
+
+def coef_index(a1: int, a2: int, a3: int) -> int:
+    """Position of the coefficient of multi-index (n - a1 - a2 - a3, a1, a2, a3)."""
+    lib = load_library()
+    i = lib.bbwadg_coef_index(a1, a2, a3)
+    if i < 0:
+        _check(i)
+    return i
 
 
 def projection_coefficients(N: int, M: int) -> np.ndarray:
@@ -228,6 +242,15 @@ class Solver:
         stream = None if c2_out is None else self._stream()
         _check(self._lib.bbwadg_project_c2(self._ctx, cb, None, ptr, stream))
 
+    def project_fn_callback(self, fn_scalar, field: int, q_out):
+        """The C-callback projection of one state field (fn_scalar(x, y, z) -> float) into
+        field `field` of the device state q_out."""
+        self._check_state(q_out, "q_out")
+        cb = C2_CALLBACK(lambda x, y, z, u: float(fn_scalar(x, y, z)))
+        _check(self._lib.bbwadg_project_fn(self._ctx, cb, None, int(field), C.c_void_p(q_out.data_ptr()),
+                                           self._stream()))
+        return q_out
+
     def set_c2(self, coef):
         c = np.ascontiguousarray(coef, dtype=np.float64)
         if c.shape != (self.K, self.Mp):
@@ -291,4 +314,47 @@ class Solver:
         self._check_state(q, "q")
         out = np.zeros(4)
         _check(self._lib.bbwadg_l2norm2(self._ctx, C.c_void_p(q.data_ptr()), _dptr(out), self._stream()))
+        return out
+
+    def l2error2(self, q, fns, k0: int = 0, k1: int | None = None, chunk: int = 16384) -> np.ndarray:
+        """Per-field squared L^2 error of q against four vectorised functions f(x, y, z),
+        over elements [k0, k1); the reference values are sampled on the host at the
+        library's rule points and handed over in pieces of `chunk` elements."""
+        import torch
+        self._check_state(q, "q")
+        k1 = self.K if k1 is None else k1
+        total = np.zeros(4)
+        out = np.zeros(4)
+        for a in range(k0, k1, chunk):
+            b = min(k1, a + chunk)
+            X = self.projection_points(self.N, a, b)
+            ex = np.stack([np.broadcast_to(np.asarray(f(X[..., 0], X[..., 1], X[..., 2]), dtype=np.float64),
+                                           X.shape[:2]) for f in fns])
+            d = torch.as_tensor(np.ascontiguousarray(ex), device="cuda")
+            _check(self._lib.bbwadg_l2error2(self._ctx, C.c_void_p(q.data_ptr()), a, b, C.c_void_p(d.data_ptr()),
+                                             _dptr(out), self._stream()))
+            total += out
+        return total
+
+    def l2error2_samples(self, q, exact, k0: int = 0, k1: int | None = None) -> np.ndarray:
+        """As l2error2, with the reference values already on the device: FP64 [4, k1-k0, nq]."""
+        import torch
+        self._check_state(q, "q")
+        k1 = self.K if k1 is None else k1
+        nq = self.projection_npoints(self.N)
+        if (not isinstance(exact, torch.Tensor) or not exact.is_cuda or exact.dtype != torch.float64
+                or tuple(exact.shape) != (4, k1 - k0, nq) or not exact.is_contiguous()):
+            raise ValueError(f"exact must be a contiguous float64 device tensor of shape (4, {k1 - k0}, {nq})")
+        out = np.zeros(4)
+        _check(self._lib.bbwadg_l2error2(self._ctx, C.c_void_p(q.data_ptr()), k0, k1, C.c_void_p(exact.data_ptr()),
+                                         _dptr(out), self._stream()))
+        return out
+
+    def energy(self, q, k0: int = 0, k1: int | None = None) -> np.ndarray:
+        """Acoustic energy terms [p^2/c^2, u^2, v^2, w^2] (each with the factor 1/2) over
+        elements [k0, k1); the energy is their sum."""
+        self._check_state(q, "q")
+        k1 = self.K if k1 is None else k1
+        out = np.zeros(4)
+        _check(self._lib.bbwadg_energy(self._ctx, C.c_void_p(q.data_ptr()), k0, k1, _dptr(out), self._stream()))
         return out

@@ -44,4 +44,21 @@ int launch_stage_f32(int N, int M, bool update, const StageArgs<float>& a, void*
 int launch_l2norm(int N, int dtype, const void* q, int64_t K, const double* J, const double* mass,
                   double* partial, int nblocks, void* stream);
 
+// Quadrature reductions over elements [k0, k1): mode 0 = squared L^2 error against
+// `exact`, mode 1 = the two halves of the acoustic energy (p^2/c^2 and |u_i|^2 terms).
+struct QuadReduceArgs {
+  const void* q;          // [4][K][Np] state, context dtype
+  const void* c2;         // [K][Mp] c^2_M coefficients, context dtype (mode 1)
+  const double* J;        // [K]
+  const double* basis;    // [Np][nq] B^N_alpha at the rule points
+  const double* basis_c2; // [Mp][nq] B^M_beta at the rule points (mode 1)
+  const double* w;        // [nq] rule weights (reference volume 4/3)
+  const double* exact;    // [4][k1-k0][nq] reference values (mode 0)
+  double* partial;        // [nblocks][4] per-block sums
+  int64_t K, k0, k1;
+  int32_t Np, Mp, nq;
+};
+int quad_reduce_blocks(int64_t nelems, int max_blocks);
+int launch_quad_reduce(int dtype, int mode, const QuadReduceArgs& a, int nblocks, void* stream);
+
 }  // namespace bbw

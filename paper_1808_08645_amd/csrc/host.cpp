@@ -175,6 +175,7 @@ struct Projector {
   int nq = 0;
   std::vector<double> P;     // [dimp][nq]
   std::vector<double> B;     // [nq][dimp] Bernstein values at the points
+  std::vector<double> w;     // [nq] rule weights (sum 4/3)
   std::vector<std::array<ld, 4>> lam;
 };
 
@@ -219,6 +220,7 @@ void build_projector(int d, Projector& pr) {
   }
   pr.B.assign((size_t)nq * np, 0);
   for (size_t i = 0; i < Bq.size(); ++i) pr.B[i] = (double)Bq[i];
+  pr.w.assign(w.begin(), w.end());
   pr.degree = d;
   pr.nq = nq;
 }
@@ -266,6 +268,11 @@ struct bbwadg_ctx {
   void* d_mass = nullptr;
   void* d_partial = nullptr;
   int nred_blocks = 0;
+  // quadrature reductions: tables at the degree-N projection rule
+  void* d_rbasis = nullptr;     // [Np][nq] B^N
+  void* d_rbasis_c2 = nullptr;  // [Mp][nq] B^M
+  void* d_rw = nullptr;         // [nq]
+  int nq_red = 0;
 };
 
 namespace {
@@ -292,7 +299,8 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 }
 
 void free_device(bbwadg_ctx* c) {
-  void** ptrs[] = {&c->d_geo, &c->d_conn, &c->d_c2, &c->d_q2, &c->d_J, &c->d_mass, &c->d_partial};
+  void** ptrs[] = {&c->d_geo,  &c->d_conn,    &c->d_c2,       &c->d_q2,  &c->d_J,
+                   &c->d_mass, &c->d_partial, &c->d_rbasis, &c->d_rbasis_c2, &c->d_rw};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -396,6 +404,43 @@ int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, d
     e = launch_stage_f32(c->N, c->M, update, a, s);
   }
   if (e != 0) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
+}
+
+// One quadrature reduction over elements [k0, k1) (mode 0: error, 1: energy); sums the
+// per-block partials on the host in block order.
+int quad_reduce(bbwadg_ctx* c, int mode, const void* q, int64_t k0, int64_t k1, const double* exact, double out[4],
+                hipStream_t s) {
+  if (k0 < 0 || k1 > c->K || k0 > k1) return fail(BBWADG_EINVAL, "bad element range");
+  for (int f = 0; f < 4; ++f) out[f] = 0.0;
+  if (k0 == k1) return 0;
+  QuadReduceArgs a{};
+  a.q = q;
+  a.c2 = c->d_c2;
+  a.J = (const double*)c->d_J;
+  a.basis = (const double*)c->d_rbasis;
+  a.basis_c2 = (const double*)c->d_rbasis_c2;
+  a.w = (const double*)c->d_rw;
+  a.exact = exact;
+  a.partial = (double*)c->d_partial;
+  a.K = c->K;
+  a.k0 = k0;
+  a.k1 = k1;
+  a.Np = c->Np;
+  a.Mp = c->Mp;
+  a.nq = c->nq_red;
+  const int nb = quad_reduce_blocks(k1 - k0, c->nred_blocks);
+  int e = launch_quad_reduce(c->dtype, mode, a, nb, s);
+  if (e) return fail(BBWADG_EHIP, "reduction launch: %s", hipGetErrorString((hipError_t)e));
+  std::vector<double> part((size_t)nb * 4);
+  hipError_t he = hipMemcpyAsync(part.data(), c->d_partial, part.size() * 8, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return fail(BBWADG_EHIP, "reduction copy: %s", hipGetErrorString(he));
+  for (int f = 0; f < 4; ++f) {
+    double acc = 0;
+    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * 4 + f];
+    out[f] = acc;
+  }
   return 0;
 }
 
@@ -571,6 +616,24 @@ int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx**
   if (!rc) rc = upload(c->d_conn, c->conn.data(), c->conn.size() * 4);
   if (!rc) rc = upload(c->d_J, c->J.data(), (size_t)K * 8);
   if (!rc) rc = upload(c->d_mass, massd.data(), massd.size() * 8);
+  if (!rc) {
+    // tables of the quadrature reductions: the degree-N projection rule, B^N and B^M there
+    const Projector& pr = get_projector(c, N);
+    const int nq = pr.nq, np = c->Np, mp = c->Mp;
+    auto AM = mi3_list(M);
+    std::vector<double> bt((size_t)np * nq), bm((size_t)mp * nq);
+    for (int qq = 0; qq < nq; ++qq) {
+      for (int i = 0; i < np; ++i) bt[(size_t)i * nq + qq] = pr.B[(size_t)qq * np + i];
+      for (int i = 0; i < mp; ++i) bm[(size_t)i * nq + qq] = (double)bernstein(M, AM[i], pr.lam[qq]);
+    }
+    c->nq_red = nq;
+    rc = dmalloc(&c->d_rbasis, bt.size() * 8);
+    if (!rc) rc = dmalloc(&c->d_rbasis_c2, bm.size() * 8);
+    if (!rc) rc = dmalloc(&c->d_rw, (size_t)nq * 8);
+    if (!rc) rc = upload(c->d_rbasis, bt.data(), bt.size() * 8);
+    if (!rc) rc = upload(c->d_rbasis_c2, bm.data(), bm.size() * 8);
+    if (!rc) rc = upload(c->d_rw, pr.w.data(), (size_t)nq * 8);
+  }
   if (rc) { free_device(c); delete c; return rc; }
   *out = c;
   return 0;
@@ -770,6 +833,69 @@ int bbwadg_l2norm2(bbwadg_ctx* c, const void* q, double out[4], void* stream) {
     out[f] = acc;
   }
   return 0;
+}
+
+int bbwadg_l2error2(bbwadg_ctx* c, const void* q, int64_t k0, int64_t k1, const double* exact, double out[4],
+                    void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !exact || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  return quad_reduce(c, 0, q, k0, k1, exact, out, (hipStream_t)stream);
+}
+
+int bbwadg_energy(bbwadg_ctx* c, const void* q, int64_t k0, int64_t k1, double out[4], void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s))) return rc;
+  return quad_reduce(c, 1, q, k0, k1, nullptr, out, s);
+}
+
+int bbwadg_project_fn(bbwadg_ctx* c, double (*fn)(double, double, double, void*), void* user, int32_t field,
+                      void* q_out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!fn || !q_out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (field < 0 || field > 3) return fail(BBWADG_EINVAL, "field %d outside [0,3]", field);
+  const Projector& pr = get_projector(c, c->N);
+  const int64_t K = c->K;
+  const int np = c->Np;
+  std::vector<double> coef((size_t)K * np);
+  const int64_t chunk = 4096;
+  std::vector<double> xyz, smp;
+  for (int64_t k0 = 0; k0 < K; k0 += chunk) {
+    int64_t k1 = std::min(K, k0 + chunk);
+    xyz.resize((size_t)(k1 - k0) * pr.nq * 3);
+    smp.resize((size_t)(k1 - k0) * pr.nq);
+    if ((rc = bbwadg_projection_points(c, c->N, k0, k1, xyz.data()))) return rc;
+    for (size_t i = 0; i < smp.size(); ++i) {
+      smp[i] = fn(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], user);
+      if (!std::isfinite(smp[i])) return fail(BBWADG_EINVAL, "non-finite sample in element %lld", (long long)(k0 + (int64_t)i / pr.nq));
+    }
+    if ((rc = bbwadg_project_samples(c, c->N, k0, k1, smp.data(), &coef[(size_t)k0 * np]))) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* dst = (char*)q_out + (size_t)field * K * np * c->rsz;
+  std::vector<float> f32;
+  const void* src = coef.data();
+  size_t bytes = coef.size() * 8;
+  if (c->dtype == BBWADG_F32) {
+    f32 = convert<float>(coef);
+    src = f32.data();
+    bytes = f32.size() * 4;
+  }
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // src is a local buffer
+  if (e != hipSuccess) return fail(BBWADG_EHIP, "state upload: %s", hipGetErrorString(e));
+  return 0;
+}
+
+int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3) {
+  if (a1 < 0 || a2 < 0 || a3 < 0) return fail(BBWADG_EINVAL, "negative multi-index entry");
+  const int s = a1 + a2 + a3;
+  if (s > kMaxDeg) return fail(BBWADG_EINVAL, "degree %d above %d", s, kMaxDeg);
+  return dimp(s - 1) + a3 * (2 * s + 3 - a3) / 2 + a2;
 }
 
 }  // extern "C"

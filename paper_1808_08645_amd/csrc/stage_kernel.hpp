@@ -291,7 +291,53 @@ void stage_kernel(const StageArgs<real> a) {
     }
   }
 
-  // Per-phase neighbour offsets (bytes, this wave's slice), derived from the packed indices.
+  // Neighbour offsets (bytes, this team's slice), computed once and kept in registers;
+  // weights are recomputed per phase from an opaque copy of the packed indices, so that
+  // the compiler does not hold one converted weight per phase and slot.
+  int o3[S3][7];  // self, up e1..e3, dn e1..e3
+#pragma unroll
+  for (int s = 0; s < S3; ++s) {
+    const int p = pa3[s];
+    const int a1 = p & 255, a3 = (p >> 16) & 255, sa = p >> 24, a2 = (p >> 8) & 255;
+    const int self = wb + (lane + TL * s) * SZ;
+    const int du = ((sa + 1) * (sa + 2) >> 1) * EW * SZ;  // D(s)
+    const int dd = ((sa * (sa + 1)) >> 1) * EW * SZ;      // D(s-1)
+    o3[s][0] = self;
+    o3[s][1] = self + du + a3 * EW * SZ;
+    o3[s][2] = o3[s][1] + EW * SZ;
+    o3[s][3] = self + du + (sa + 2) * EW * SZ;
+    o3[s][4] = a1 > 0 ? self - dd - a3 * EW * SZ : self;
+    o3[s][5] = a2 > 0 ? self - dd - (a3 + 1) * EW * SZ : self;
+    o3[s][6] = a3 > 0 ? self - dd - (sa + 1) * EW * SZ : self;
+  }
+  int o2[S2][5];  // self, up e1, e2, dn e1, e2
+#pragma unroll
+  for (int t = 0; t < S2; ++t) {
+    const int p = pb2[t];
+    const int b1 = p & 255, b2 = (p >> 8) & 255, tb = p >> 16;
+    const int item = lane + TL * t;
+    const int self = wb + (item + item / CH) * SZ;  // unit b*CHP + ch with CHP = CH + 1
+    o2[t][0] = self;
+    o2[t][1] = self + (tb + 1) * CHP * SZ;
+    o2[t][2] = self + (tb + 2) * CHP * SZ;
+    o2[t][3] = b1 > 0 ? self - tb * CHP * SZ : self;
+    o2[t][4] = b2 > 0 ? self - (tb + 1) * CHP * SZ : self;
+  }
+  int lpo[S3N][4];  // lift-chain position of alpha on face f
+#pragma unroll
+  for (int s = 0; s < S3N; ++s) {
+    const int p = pa3[s];
+    const int a1 = p & 255, a2 = (p >> 8) & 255, a3 = (p >> 16) & 255, sa = p >> 24;
+    const int e = (lane + TL * s) - ((lane + TL * s) / EW) * EW;
+    const int af[4] = {N - sa, a1, a2, a3};
+    const int b1f[4] = {a2, a2, a1, a1}, b2f[4] = {a3, a3, a3, a2};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int rem = N - af[f];  // level alpha_f of face f's chain starts at dimp(N) - dimp(N - alpha_f)
+      lpo[s][f] = wb + ((af[f] >= 0 ? NP - (rem + 1) * (rem + 2) * (rem + 3) / 6 + g2(b1f[f], b2f[f]) : 0) * CHP +
+                        f * EW + e) * SZ;
+    }
+  }
   struct N3 {
     int self, up[3], dn[3], a1, a2, a3, sa;
   };
@@ -302,15 +348,13 @@ void stage_kernel(const StageArgs<real> a) {
     r.a2 = (p >> 8) & 255;
     r.a3 = (p >> 16) & 255;
     r.sa = p >> 24;
-    r.self = wb + (lane + TL * s) * SZ;
-    const int du = ((r.sa + 1) * (r.sa + 2) >> 1) * EW * SZ;  // D(s)
-    const int dd = ((r.sa * (r.sa + 1)) >> 1) * EW * SZ;      // D(s-1)
-    r.up[0] = r.self + du + r.a3 * EW * SZ;
-    r.up[1] = r.up[0] + EW * SZ;
-    r.up[2] = r.self + du + (r.sa + 2) * EW * SZ;
-    r.dn[0] = r.a1 > 0 ? r.self - dd - r.a3 * EW * SZ : r.self;
-    r.dn[1] = r.a2 > 0 ? r.self - dd - (r.a3 + 1) * EW * SZ : r.self;
-    r.dn[2] = r.a3 > 0 ? r.self - dd - (r.sa + 1) * EW * SZ : r.self;
+    r.self = o3[s][0];
+    r.up[0] = o3[s][1];
+    r.up[1] = o3[s][2];
+    r.up[2] = o3[s][3];
+    r.dn[0] = o3[s][4];
+    r.dn[1] = o3[s][5];
+    r.dn[2] = o3[s][6];
     return r;
   };
   struct N2 {
@@ -322,12 +366,11 @@ void stage_kernel(const StageArgs<real> a) {
     r.b1 = p & 255;
     r.b2 = (p >> 8) & 255;
     r.tb = p >> 16;
-    const int item = lane + TL * t;
-    r.self = wb + (item + item / CH) * SZ;  // unit b*CHP + ch with CHP = CH + 1
-    r.up[0] = r.self + (r.tb + 1) * CHP * SZ;
-    r.up[1] = r.self + (r.tb + 2) * CHP * SZ;
-    r.dn[0] = r.b1 > 0 ? r.self - r.tb * CHP * SZ : r.self;
-    r.dn[1] = r.b2 > 0 ? r.self - (r.tb + 1) * CHP * SZ : r.self;
+    r.self = o2[t][0];
+    r.up[0] = o2[t][1];
+    r.up[1] = o2[t][2];
+    r.dn[0] = o2[t][3];
+    r.dn[1] = o2[t][4];
     return r;
   };
 
@@ -575,16 +618,10 @@ void stage_kernel(const StageArgs<real> a) {
       const int item = lane + TL * s;
       if (item < EW * NP) {
         const int e = item - (item / EW) * EW;
-        const int p = opq(pa3[s]);
-        const int a1 = p & 255, a2 = (p >> 8) & 255, a3 = (p >> 16) & 255, sa = p >> 24;
-        const int af[4] = {N - sa, a1, a2, a3};
-        const int b1f[4] = {a2, a2, a1, a1}, b2f[4] = {a3, a3, a3, a2};
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
-          // level alpha_f of face f's chain starts at dimp(N) - dimp(N - alpha_f)
-          const int rem = N - af[f];
-          const int lpf = wb + ((NP - (rem + 1) * (rem + 2) * (rem + 3) / 6 + g2(b1f[f], b2f[f])) * CHP + f * EW + e) * SZ;
+          const int lpf = lpo[s][f];
           const real sc = at(gf);
           const real lpv = at(lpf + BC);
           const real luv = at(lpf + BC + 4 * EW * SZ) * sc;

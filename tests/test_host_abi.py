@@ -30,7 +30,7 @@ def bb():
 
 def test_library_exports_every_declared_symbol(bb):
     header = open(os.path.join(ROOT, "include", "bbwadg.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(bbwadg_\w+)\s*\(", header, re.M))
+    declared = set(re.findall(r"^\s*(?:int|int32_t|const char\*)\s+(bbwadg_\w+)\s*\(", header, re.M))
     assert declared, "no declarations parsed"
     lib = C.CDLL(bb.LIB_PATH)
     for name in declared:
@@ -158,3 +158,18 @@ def test_error_paths(bb):
     assert lib.bbwadg_rhs(s._ctx, None, None, 0.0, None) == -1
     assert lib.bbwadg_step(s._ctx, None, None, 0.0, 0.1, 1, None) == -1
     assert b"host-only" in lib.bbwadg_last_error()
+    out = (C.c_double * 4)()
+    assert lib.bbwadg_energy(s._ctx, None, 0, s.K, out, None) == -1
+    assert lib.bbwadg_l2error2(s._ctx, None, 0, s.K, None, out, None) == -1
+    assert lib.bbwadg_project_fn(s._ctx, bb.bbwadg.C2_CALLBACK(lambda x, y, z, u: 0.0), None, 0, None, None) == -1
+    assert b"host-only" in lib.bbwadg_last_error()
+    for bad in [(-1, 0, 0), (0, -2, 1), (5, 5, 4)]:
+        assert lib.bbwadg_coef_index(*bad) == -1
+
+
+def test_coef_index_matches_documented_order(bb):
+    """bbwadg_coef_index against the oracle's enumeration of the multi-indices."""
+    from oracle.basis import multi_indices
+    for N in (1, 4, 9, 13):
+        for i, (a0, a1, a2, a3) in enumerate(multi_indices(N)):
+            assert bb.coef_index(a1, a2, a3) == i
