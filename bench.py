@@ -52,7 +52,7 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(dtype="f64"):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on
     the current kernel source; otherwise None."""
     try:
@@ -62,7 +62,7 @@ def measured_traffic():
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch_f64")
+    return t.get("bytes_per_launch_" + dtype)
 
 
 def setup(dtype):
@@ -161,7 +161,7 @@ def main():
     word = 4 if args.fp32_only else 8
     alg = algorithmic_bytes_per_element(N, M, word) * K
     achieved = alg / (kernel_ms * 1e-3) / 1e9
-    traffic = None if args.fp32_only else measured_traffic()
+    traffic = measured_traffic("f32" if args.fp32_only else "f64")
     value = dofs * args.steps / (ms * 1e-3) / 1e9
     out.update({
         "metric": "GDOF-updates/s per RK step (FP32 vs FP64) + % HBM peak, at stated L2 error",
@@ -204,7 +204,8 @@ def main():
                        "rel_l2_vs_fp64_per_field": rel_fn,
                        "rel_coef_l2_vs_fp64_per_field": rel,
                        "alg_frac_hbm": algorithmic_bytes_per_element(N, M, 4) * K /
-                       ((ms32 / (5 * args.steps)) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                       ((ms32 / (5 * args.steps)) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "traffic": measured_traffic("f32")}
     out["l2_error"] = {"fp64_vs_oracle": "<= 1e-11 relative L2 per field (parity tests)",
                        "fp32_vs_fp64": out.get("fp32", {}).get("rel_l2_vs_fp64_per_field")}
     if not args.no_cpu_baseline:
