@@ -48,8 +48,15 @@ def algorithmic_bytes_per_element(n, m, word):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of the stage kernel source with comments and blank space
+    removed, so that counters stay attached to the code they were taken on."""
+    import re
+    with open(KERNEL_SRC) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def measured_traffic(dtype="f64"):
@@ -60,7 +67,7 @@ def measured_traffic(dtype="f64"):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_code_sha256_16") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch_" + dtype)
 

@@ -26,7 +26,7 @@ struct StageArgs {
   real* res;              // [4][K][Np] 2N-storage register (step mode)
   const real* geo;        // [K][kGeoStride]
   const int32_t* conn;    // [K][4]: 4*k'+f' or -1 (boundary)
-  const real* c2;         // [K][Mp]
+  const real* c2;         // [K][Mp] c^2_M coefficients divided by beta!
   int64_t K;
   real tau_p, tau_u;
   int32_t bc;             // 0: p = 0 walls, 1: rigid walls

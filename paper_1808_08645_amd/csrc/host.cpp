@@ -262,7 +262,8 @@ struct bbwadg_ctx {
   size_t rsz = 8;
   void* d_geo = nullptr;
   void* d_conn = nullptr;
-  void* d_c2 = nullptr;
+  void* d_c2 = nullptr;   // [K][Mp] c^2_M coefficients (dtype)
+  void* d_c2k = nullptr;  // [K][Mp] c^2_M coefficients / beta! (dtype): the stage kernel's copy
   void* d_q2 = nullptr;
   void* d_J = nullptr;
   void* d_mass = nullptr;
@@ -299,8 +300,8 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 }
 
 void free_device(bbwadg_ctx* c) {
-  void** ptrs[] = {&c->d_geo,  &c->d_conn,    &c->d_c2,       &c->d_q2,  &c->d_J,
-                   &c->d_mass, &c->d_partial, &c->d_rbasis, &c->d_rbasis_c2, &c->d_rw};
+  void** ptrs[] = {&c->d_geo,     &c->d_conn,   &c->d_c2,         &c->d_c2k, &c->d_q2, &c->d_J,
+                   &c->d_mass,    &c->d_partial, &c->d_rbasis, &c->d_rbasis_c2, &c->d_rw};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -339,18 +340,29 @@ int check_c2(const bbwadg_ctx* ctx, const double* coef, int64_t k0, int64_t k1) 
   return 0;
 }
 
+// Upload c^2_M (as stored) and the stage kernel's copy scaled by 1/beta!: the product of
+// eq. (mcoeff) is evaluated in that scaled form.
 int sync_c2(bbwadg_ctx* ctx, hipStream_t s) {
   if (!ctx->c2_set) return fail(BBWADG_EC2, "c^2 not set (call bbwadg_project_c2 or bbwadg_set_c2)");
   if (!ctx->c2_dirty) return 0;
+  const int mp = ctx->Mp;
+  auto B = mi3_list(ctx->M);
+  std::vector<double> inv(mp);
+  for (int b = 0; b < mp; ++b)
+    inv[b] = (double)(1.0L / (factl(B[b][0]) * factl(B[b][1]) * factl(B[b][2]) * factl(B[b][3])));
+  std::vector<double> scaled(ctx->c2.size());
+  for (size_t i = 0; i < scaled.size(); ++i) scaled[i] = ctx->c2[i] * inv[i % mp];
   hipError_t e;
   if (ctx->dtype == BBWADG_F64) {
     e = hipMemcpyAsync(ctx->d_c2, ctx->c2.data(), ctx->c2.size() * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_c2k, scaled.data(), scaled.size() * 8, hipMemcpyHostToDevice, s);
   } else {
-    std::vector<float> f = convert<float>(ctx->c2);
+    std::vector<float> f = convert<float>(ctx->c2), fk = convert<float>(scaled);
     e = hipMemcpyAsync(ctx->d_c2, f.data(), f.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // f is a local buffer
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->d_c2k, fk.data(), fk.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // f, fk are local buffers
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // scaled is a local buffer
   if (e != hipSuccess) return fail(BBWADG_EHIP, "c^2 upload: %s", hipGetErrorString(e));
   ctx->c2_dirty = false;
   return 0;
@@ -361,7 +373,7 @@ StageArgs<real> make_args(const bbwadg_ctx* c) {
   StageArgs<real> a{};
   a.geo = (const real*)c->d_geo;
   a.conn = (const int32_t*)c->d_conn;
-  a.c2 = (const real*)c->d_c2;
+  a.c2 = (const real*)c->d_c2k;
   a.K = c->K;
   a.tau_p = (real)c->tau_p;
   a.tau_u = (real)c->tau_u;
@@ -598,7 +610,8 @@ int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx**
   const size_t qbytes = (size_t)4 * K * c->Np * rs;
   c->nred_blocks = 1024;
   if ((rc = dmalloc(&c->d_geo, geo.size() * rs)) || (rc = dmalloc(&c->d_conn, c->conn.size() * 4)) ||
-      (rc = dmalloc(&c->d_c2, (size_t)K * c->Mp * rs)) || (rc = dmalloc(&c->d_q2, qbytes)) ||
+      (rc = dmalloc(&c->d_c2, (size_t)K * c->Mp * rs)) || (rc = dmalloc(&c->d_c2k, (size_t)K * c->Mp * rs)) ||
+      (rc = dmalloc(&c->d_q2, qbytes)) ||
       (rc = dmalloc(&c->d_J, (size_t)K * 8)) || (rc = dmalloc(&c->d_mass, (size_t)c->Np * c->Np * 8)) ||
       (rc = dmalloc(&c->d_partial, (size_t)c->nred_blocks * 4 * 8))) {
     free_device(c);

@@ -17,7 +17,11 @@
 //   lift positions, product positions) once, into registers; the element loop reads no
 //   index table.
 // * A wavefront owns EW elements at a time and keeps every intermediate in its own slice
-//   of LDS; phases synchronise at wavefront level only.
+//   of LDS; phases synchronise at wavefront level only. Since a lane holds the same
+//   position at every degree, each stencil's own-position term is taken from the lane's
+//   registers and only neighbour terms are read from LDS.
+// * The WADG levels are kept scaled by a1!a2!a3! (reductions) or its inverse (elevations),
+//   which leaves a single weight per stencil.
 // * Waves are persistent: each XCD processes a contiguous range of elements so that face
 //   neighbours are found in that XCD's L2, and the next element group's state, geometry
 //   and c^2 are prefetched into registers while the current one is computed.
@@ -50,6 +54,13 @@ __device__ __forceinline__ int opq(int x) {
 }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Load through the constant address space: with a wave-uniform address this is a scalar
+// load into SGPRs (per-element data of a team that owns one element).
+template <typename T>
+__device__ __forceinline__ T uload(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
 // Graded position of (a1, a2, a3): dimp(s-1) + a3 (2s+3-a3)/2 + a2, s = a1+a2+a3.
 __host__ __device__ constexpr int g3(int a1, int a2, int a3) {
   return dimp(a1 + a2 + a3 - 1) + a3 * (2 * (a1 + a2 + a3) + 3 - a3) / 2 + a2;
@@ -63,10 +74,11 @@ constexpr int chain_off(int N, int i) {
   for (int l = 0; l < i; ++l) s += dim2(N - l);
   return s;
 }
-// Start of level j (degree N-j) in the concatenated telescoping levels.
+// Start of level j (degree N-j) in the concatenated telescoping levels. Levels j >= 1 are
+// preceded by one position that stays zero: an elevation reads it for a missing neighbour.
 constexpr int lev_off(int N, int j) {
   int s = 0;
-  for (int i = 0; i < j; ++i) s += dimp(N - i);
+  for (int i = 0; i < j; ++i) s += dimp(N - i) + 1;
   return s;
 }
 __host__ __device__ constexpr long long fact(int n) {
@@ -113,6 +125,17 @@ constexpr int waves_per_team() {
   return dimp(N) <= 64 ? 1 : (dimp(N) + 63) / 64 > 4 ? 4 : (dimp(N) + 63) / 64;
 }
 
+// Product positions are kept in registers when MP * S3 is at most this, else derived per use.
+#ifndef BBW_MUL_REGS_MAX
+#define BBW_MUL_REGS_MAX 40
+#endif
+
+// Face-chain layout: unpadded rows with the channel XOR-swizzled by the row (1), or an odd
+// row pitch (0).
+#ifndef BBW_CHAIN_SWZ
+#define BBW_CHAIN_SWZ 1
+#endif
+
 template <typename real, int N, int M, int EW>
 struct StageLayout {
   static constexpr int TW = waves_per_team<N>();     // waves per team (one team owns EW elements)
@@ -127,27 +150,32 @@ struct StageLayout {
   static constexpr int SF = cdiv(4 * EW * NFP, TL);    // flux slots (4 faces per element)
   static constexpr int SPW = cdiv(EW * PW, TL);        // per-element scalar loads per lane
   static constexpr int CH = 8 * EW;                    // chain channels: (p, u) x 4 faces x EW
-  static constexpr int CHP = CH % 2 ? CH : CH + 1;     // padded (odd) channel stride in LDS
+  // Face-chain arrays hold one real per unit b*CHP + slot(b, channel). With a power-of-two
+  // channel count the rows are unpadded and the channel is XOR-swizzled by the low bits of
+  // the row, so that lanes reading one channel from different rows spread over the banks
+  // while a row stays one contiguous run; otherwise the row pitch is odd.
+  static constexpr bool SWZ = BBW_CHAIN_SWZ && (CH & (CH - 1)) == 0;
+  static constexpr int CHP = SWZ ? CH : (CH % 2 ? CH : CH + 1);
+  static __host__ __device__ constexpr int cunit(int row, int ch) { return row * CHP + (SWZ ? (ch ^ (row & 7)) : ch); }
   // Per-wave LDS slice, in reals. A 3D array holds one real per unit pos*EW + e; a field
-  // array is 4 such planes. Face-chain arrays hold one real per unit b*CHP + channel (an
-  // odd stride, so that lanes reading one channel at consecutive b hit distinct banks).
+  // array is 4 such planes.
   static constexpr int OFF_P = 0;                          // [EW][25] geometry, [EW][MP] c^2/beta!
   static constexpr int OFF_Q = cdiv(EW * PW, 2) * 2;       // 4 planes [NP*EW] state
   static constexpr int PLQ = EW * NP;
-  static constexpr int OFF_A = OFF_Q + 4 * PLQ;            // Y: 4 planes [NP1*EW] | F [NFP*CHP], T [NFP1*CHP] | R [NP*EW]
+  static constexpr int OFF_A = cdiv(OFF_Q + 4 * PLQ, 8) * 8;  // Y: 4 planes [NP1*EW] | F [NFP*CHP], T [NFP1*CHP] | R [NP*EW]
   static constexpr int PLY = EW * NP1;
   static constexpr int SA = cmax(4 * PLY + EW * (NP - NP1), CHP * (NFP + NFP1));
-  static constexpr int OFF_B = OFF_A + SA;                 // chain [NP*CHP] | H, H1, levels
-  static constexpr int SB = cmax(CHP * NP, EW * (NH + NH1 + LEV) + 4 * EW);
+  static constexpr int OFF_B = cdiv(OFF_A + SA, 8) * 8;    // chain [NP*CHP] | H, H1, levels
+  static constexpr int SB = cmax(CHP * NP, EW * (NH + NH1 + LEV) + 4 * EW);  // LEV includes the level guards
   static constexpr int OFF_Z = OFF_B + SB;                 // a real that stays zero
-  static constexpr int TOTAL = cdiv(OFF_Z + 2, 2) * 2;
+  static constexpr int TOTAL = cdiv(OFF_Z + 2, 8) * 8;  // slices stay 8-real aligned
   static constexpr int BYTES = TOTAL * (int)sizeof(real);
   // teams per workgroup: single-wave teams share a workgroup (up to 4 within 64 KiB of LDS);
   // a multi-wave team is a workgroup of its own, synchronised by the workgroup barrier
   static constexpr int TPB = TW > 1 ? 1 : cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
   static constexpr int WPB = TW * TPB;
   // product positions kept in registers when they are few, computed per use otherwise
-  static constexpr bool MUL_REGS = MP * S3 <= 40;
+  static constexpr bool MUL_REGS = MP * S3 <= BBW_MUL_REGS_MAX;
   // waves per SIMD that LDS allows (160 KiB per CU, 4 SIMDs); registers are budgeted for
   // the same occupancy, at most 4
   static constexpr int LDS_WAVES = (163840 / (BYTES * TPB)) * WPB / 4;
@@ -164,6 +192,19 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
     default: return g3(b1, b2, 0);
   }
 }
+
+
+// Which phases take their own-position ("self") term from registers instead of LDS: bit 0
+// the volume's state, bit 1 the derivative planes, bit 2 the face chain, bit 3 the WADG
+// levels.
+#ifndef BBW_CARRY
+#define BBW_CARRY 15
+#endif
+
+// Per-element scalars of a one-element team through scalar loads (1) or the LDS copy (0).
+#ifndef BBW_SGPR_ELEM
+#define BBW_SGPR_ELEM 1
+#endif
 
 // Optional occupancy target (waves per SIMD) for the register allocator; 0 leaves the
 // choice to the compiler.
@@ -213,11 +254,14 @@ void stage_kernel(const StageArgs<real> a) {
 
   // ---- per-lane index registers (computed once) -------------------------------------
   // 3D slot s holds unit lane + 64 s = pos*EW + e, pos the graded position of (a1,a2,a3).
-  // Only the packed multi-index is kept; stencil neighbours follow from the graded order:
+  // Stencil neighbours follow from the graded order:
   //   pos(a+e1) = pos + D(s) + a3, pos(a+e2) = pos + D(s) + a3 + 1, pos(a+e3) = pos + D(s) + s + 2
   // with D(s) = (s+1)(s+2)/2 and s = a1+a2+a3 (and the same relations read backwards).
   int pa3[S3];
-  real fac3[S3N], facH[S3];
+  // fac3 = 1/alpha!, facH = gamma! A(gamma) / C(N+M, N), aF = A(alpha) and iA2 = 1/A(alpha)^2
+  // with A(alpha) = a1! a2! a3!: the WADG levels are kept scaled by A (reductions) or by
+  // 1/A (elevations), which leaves one weight per stencil.
+  real fac3[S3N], facH[S3], aF[S3N], iA2[S3N];
   // product positions, two 16-bit byte offsets per register
   int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? (MP + 1) / 2 : 1];
 #pragma unroll
@@ -229,10 +273,13 @@ void stage_kernel(const StageArgs<real> a) {
     const int sa = a1 + a2 + a3;
     pa3[s] = a1 | (a2 << 8) | (a3 << 16) | (sa << 24);
     const int a0N = N - sa, a0H = N + M - sa;
-    facH[s] = real(double(fact(a0H) * fact(a1) * fact(a2) * fact(a3)) / double(binom(N + M, N)));
+    const double Af = double(fact(a1) * fact(a2) * fact(a3));
+    facH[s] = real(double(fact(a0H)) * Af * Af / double(binom(N + M, N)));
     if (s < S3N) {
       const int sN = s < S3N ? s : 0;
       fac3[sN] = (a0N >= 0) ? real(1) / real(fact(a0N) * fact(a1) * fact(a2) * fact(a3)) : real(0);
+      aF[sN] = real(Af);
+      iA2[sN] = real(1.0 / (Af * Af));
     }
     if constexpr (L::MUL_REGS) {
       int b = 0;  // beta in the graded coefficient order of c^2
@@ -277,24 +324,11 @@ void stage_kernel(const StageArgs<real> a) {
              (face_pos(3, b0, b1, b2) << 24);
     ffe[u] = fe | (m << 16);
   }
-  // factor 1/beta! of the c^2 coefficient this lane stages (product in scaled form)
-  real pscale[SPW];
-#pragma unroll
-  for (int r = 0; r < SPW; ++r) {
-    const int i = lane + TL * r;
-    pscale[r] = real(1);
-    if (i >= 25 * EW && i < PW * EW) {
-      const int bpos = (i - 25 * EW) % MP;
-      int b1, b2, b3;
-      pos3(bpos, b1, b2, b3);
-      pscale[r] = real(1) / real(fact(M - b1 - b2 - b3) * fact(b1) * fact(b2) * fact(b3));
-    }
-  }
-
   // Neighbour offsets (bytes, this team's slice), computed once and kept in registers;
-  // weights are recomputed per phase from an opaque copy of the packed indices, so that
+  // weights are recomputed per phase from an opaque copy of the packed multi-index, so that
   // the compiler does not hold one converted weight per phase and slot.
-  int o3[S3][7];  // self, up e1..e3, dn e1..e3
+  int o3p[S3][7], o2p[S2][5];
+  int o3[7];
 #pragma unroll
   for (int s = 0; s < S3; ++s) {
     const int p = pa3[s];
@@ -302,26 +336,35 @@ void stage_kernel(const StageArgs<real> a) {
     const int self = wb + (lane + TL * s) * SZ;
     const int du = ((sa + 1) * (sa + 2) >> 1) * EW * SZ;  // D(s)
     const int dd = ((sa * (sa + 1)) >> 1) * EW * SZ;      // D(s-1)
-    o3[s][0] = self;
-    o3[s][1] = self + du + a3 * EW * SZ;
-    o3[s][2] = o3[s][1] + EW * SZ;
-    o3[s][3] = self + du + (sa + 2) * EW * SZ;
-    o3[s][4] = a1 > 0 ? self - dd - a3 * EW * SZ : self;
-    o3[s][5] = a2 > 0 ? self - dd - (a3 + 1) * EW * SZ : self;
-    o3[s][6] = a3 > 0 ? self - dd - (sa + 1) * EW * SZ : self;
+    o3[0] = self;
+    o3[1] = self + du + a3 * EW * SZ;
+    o3[2] = o3[1] + EW * SZ;
+    o3[3] = self + du + (sa + 2) * EW * SZ;
+    // a missing neighbour (a_k = 0) is position -1 of the array read: the zero guard in
+    // front of a telescoping level, a finite value elsewhere (where its weight is zero)
+    const int e = (lane + TL * s) - ((lane + TL * s) / EW) * EW;
+    const int none = wb + (e - EW) * SZ;
+    o3[4] = a1 > 0 ? self - dd - a3 * EW * SZ : none;
+    o3[5] = a2 > 0 ? self - dd - (a3 + 1) * EW * SZ : none;
+    o3[6] = a3 > 0 ? self - dd - (sa + 1) * EW * SZ : none;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) o3p[s][k] = o3[k];  // self, up e1..e3, dn e1..e3
   }
-  int o2[S2][5];  // self, up e1, e2, dn e1, e2
+  int o2[5];
 #pragma unroll
   for (int t = 0; t < S2; ++t) {
     const int p = pb2[t];
     const int b1 = p & 255, b2 = (p >> 8) & 255, tb = p >> 16;
     const int item = lane + TL * t;
-    const int self = wb + (item + item / CH) * SZ;  // unit b*CHP + ch with CHP = CH + 1
-    o2[t][0] = self;
-    o2[t][1] = self + (tb + 1) * CHP * SZ;
-    o2[t][2] = self + (tb + 2) * CHP * SZ;
-    o2[t][3] = b1 > 0 ? self - tb * CHP * SZ : self;
-    o2[t][4] = b2 > 0 ? self - (tb + 1) * CHP * SZ : self;
+    const int row = item / CH, ch = item - (item / CH) * CH;
+    const int self = wb + L::cunit(row, ch) * SZ;
+    o2[0] = self;
+    o2[1] = wb + L::cunit(row + tb + 1, ch) * SZ;
+    o2[2] = wb + L::cunit(row + tb + 2, ch) * SZ;
+    o2[3] = b1 > 0 ? wb + L::cunit(row - tb, ch) * SZ : self;
+    o2[4] = b2 > 0 ? wb + L::cunit(row - tb - 1, ch) * SZ : self;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) o2p[t][k] = o2[k];  // self, up e1, e2, dn e1, e2
   }
   int lpo[S3N][4];  // lift-chain position of alpha on face f
 #pragma unroll
@@ -334,8 +377,10 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       const int rem = N - af[f];  // level alpha_f of face f's chain starts at dimp(N) - dimp(N - alpha_f)
-      lpo[s][f] = wb + ((af[f] >= 0 ? NP - (rem + 1) * (rem + 2) * (rem + 3) / 6 + g2(b1f[f], b2f[f]) : 0) * CHP +
-                        f * EW + e) * SZ;
+      // level base + the (swizzled) unit of the local row; zero-weighted slots use row 0
+      const bool ok = af[f] >= 0;
+      const int lev = ok ? NP - (rem + 1) * (rem + 2) * (rem + 3) / 6 : 0;
+      lpo[s][f] = wb + (lev * CHP + L::cunit(ok ? g2(b1f[f], b2f[f]) : 0, f * EW + e)) * SZ;
     }
   }
   struct N3 {
@@ -348,13 +393,13 @@ void stage_kernel(const StageArgs<real> a) {
     r.a2 = (p >> 8) & 255;
     r.a3 = (p >> 16) & 255;
     r.sa = p >> 24;
-    r.self = o3[s][0];
-    r.up[0] = o3[s][1];
-    r.up[1] = o3[s][2];
-    r.up[2] = o3[s][3];
-    r.dn[0] = o3[s][4];
-    r.dn[1] = o3[s][5];
-    r.dn[2] = o3[s][6];
+    r.self = o3p[s][0];
+    r.up[0] = o3p[s][1];
+    r.up[1] = o3p[s][2];
+    r.up[2] = o3p[s][3];
+    r.dn[0] = o3p[s][4];
+    r.dn[1] = o3p[s][5];
+    r.dn[2] = o3p[s][6];
     return r;
   };
   struct N2 {
@@ -366,11 +411,11 @@ void stage_kernel(const StageArgs<real> a) {
     r.b1 = p & 255;
     r.b2 = (p >> 8) & 255;
     r.tb = p >> 16;
-    r.self = o2[t][0];
-    r.up[0] = o2[t][1];
-    r.up[1] = o2[t][2];
-    r.dn[0] = o2[t][3];
-    r.dn[1] = o2[t][4];
+    r.self = o2p[t][0];
+    r.up[0] = o2p[t][1];
+    r.up[1] = o2p[t][2];
+    r.dn[0] = o2p[t][3];
+    r.dn[1] = o2p[t][4];
     return r;
   };
 
@@ -381,6 +426,10 @@ void stage_kernel(const StageArgs<real> a) {
   // ---- prefetch of the next element group ------------------------------------------------
   real qn[4][S3N], pn[SPW];
   int cn[SF];
+  // Every load below is unconditional: lanes without an item read a valid stand-in address
+  // (element k0, which exists) and their value is discarded or replaced where it is used.
+  // Loads under divergent control flow would make later writes to the same registers wait
+  // for all outstanding loads, which would expose the latency that the prefetch hides.
   auto prefetch = [&](int64_t g) {
     const int64_t k0 = g * EW;
 #pragma unroll
@@ -388,26 +437,25 @@ void stage_kernel(const StageArgs<real> a) {
       const int item = lane + TL * s;
       const int e = item - (item / EW) * EW, pos = item / EW;
       const bool ok = item < EW * NP && k0 + e < K;
+      const size_t idx = ok ? (size_t)(k0 + e) * NP + pos : (size_t)k0 * NP;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) qn[f][s] = ok ? qin[((size_t)f * K + k0 + e) * NP + pos] : real(0);
+      for (int f = 0; f < 4; ++f) qn[f][s] = qin[(size_t)f * K * NP + idx];
     }
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
       const int i = lane + TL * r;
-      real v = real(0);
-      if (i < 25 * EW) {
-        if (k0 + i / 25 < K) v = a.geo[k0 * kGeoStride + i];
-      } else if (i < PW * EW) {
-        const int j = i - 25 * EW;
-        if (k0 + j / MP < K) v = a.c2[k0 * MP + j];
-      }
-      pn[r] = v;
+      const int j = i - 25 * EW;
+      const bool geo_ok = i < 25 * EW && k0 + i / 25 < K;
+      const bool c2_ok = i >= 25 * EW && i < PW * EW && k0 + j / MP < K;
+      const real* src = geo_ok ? a.geo + k0 * kGeoStride + i : (c2_ok ? a.c2 + k0 * MP + j : a.geo + k0 * kGeoStride);
+      pn[r] = *src;
     }
 #pragma unroll
     for (int u = 0; u < SF; ++u) {
       const int item = lane + TL * u;
       const int fe = ffe[u] & 0xFFFF, f = fe / EW, e = fe - (fe / EW) * EW;
-      cn[u] = (item < 4 * EW * NFP && k0 + e < K) ? a.conn[(k0 + e) * 4 + f] : -1;
+      const bool ok = item < 4 * EW * NFP && k0 + e < K;
+      cn[u] = a.conn[ok ? (k0 + e) * 4 + f : k0 * 4];  // a valid id or -1 either way
     }
   };
 
@@ -416,6 +464,19 @@ void stage_kernel(const StageArgs<real> a) {
 
   for (; g < gend; g += waves_per_xcd) {
     const int64_t k0 = g * EW;
+    // per-element scalars: geometry record and c^2/beta!; a one-element team reads them with
+    // scalar loads (the lines were brought in by the previous iteration's prefetch), larger
+    // groups from their LDS copy
+    const real* const gk = a.geo + k0 * kGeoStride;
+    const real* const ck = a.c2 + k0 * MP;
+    auto geo_at = [&](int e, int i) -> real {
+      if constexpr (EW == 1 && BBW_SGPR_ELEM) return uload(gk + i);
+      else return at(wb + BP + (e * 25 + i) * SZ);
+    };
+    auto c2_at = [&](int e, int b) -> real {
+      if constexpr (EW == 1 && BBW_SGPR_ELEM) return uload(ck + b);
+      else return at(wb + BP + (25 * EW + e * MP + b) * SZ);
+    };
     if constexpr (L::MUL_REGS) {  // keep unpacking of the product positions inside the loop
 #pragma unroll
       for (int s = 0; s < S3; ++s)
@@ -426,14 +487,22 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
       const int i = lane + TL * r;
-      if (i < PW * EW) at(wb + BP + i * SZ) = pn[r] * pscale[r];
+      const bool ok = i < 25 * EW ? k0 + i / 25 < K : k0 + (i - 25 * EW) / MP < K;
+      if (i < PW * EW) at(wb + BP + i * SZ) = ok ? pn[r] : real(0);
     }
+    // A lane keeps the value it writes at its own position when the next phase reads that
+    // position again ("self" terms below): coefficient positions are the same at every
+    // degree, so the value is already in the lane's registers.
+    real qcur[4][S3N];
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
       const int item = lane + TL * s;
+      const bool ok = k0 + (item - (item / EW) * EW) < K;
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
-        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = qn[f][s];
+      for (int f = 0; f < 4; ++f) {
+        qcur[f][s] = ok ? qn[f][s] : real(0);
+        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = qcur[f][s];
+      }
     }
     // ---- issue this group's neighbour traces, then the next prefetch ---------------------
     real nb[4][SF];
@@ -442,16 +511,13 @@ void stage_kernel(const StageArgs<real> a) {
     for (int u = 0; u < SF; ++u) {
       const int c = cn[u];
       cur_conn[u] = c;
-      if (c >= 0) {
-        const size_t base = (size_t)(c >> 2) * NP + ((fnb[u] >> (8 * (c & 3))) & 255);
-        const size_t fs = (size_t)K * NP;
-        nb[0][u] = qin[base];
-        nb[1][u] = qin[base + fs];
-        nb[2][u] = qin[base + 2 * fs];
-        nb[3][u] = qin[base + 3 * fs];
-      } else {
-        nb[0][u] = nb[1][u] = nb[2][u] = nb[3][u] = real(0);
-      }
+      // boundary faces (c < 0) read this group's first coefficient; the value is not used
+      const size_t base = c >= 0 ? (size_t)(c >> 2) * NP + ((fnb[u] >> (8 * (c & 3))) & 255) : (size_t)k0 * NP;
+      const size_t fs = (size_t)K * NP;
+      nb[0][u] = qin[base];
+      nb[1][u] = qin[base + fs];
+      nb[2][u] = qin[base + 2 * fs];
+      nb[3][u] = qin[base + 3 * fs];
     }
     const int64_t gnext = g + waves_per_xcd;
     if (gnext < gend) prefetch(gnext);
@@ -460,18 +526,20 @@ void stage_kernel(const StageArgs<real> a) {
     // ---- volume: reference derivatives at degree N-1 -----------------------------------
     // Y planes: -dp/dx, -dp/dy, -dp/dz, -div u at degree N-1 (times N/2)
     constexpr real half_n = real(N) / real(2);
+    real ycar[4][S3N];
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) ycar[0][s] = ycar[1][s] = ycar[2][s] = ycar[3][s] = real(0);
 #pragma unroll
     for (int s = 0; s < S3; ++s) {
       const int item = lane + TL * s;
       if (s * TL < EW * NP1 && item < EW * NP1) {
         const int e = item - (item / EW) * EW;
-        const int gm = wb + BP + e * 25 * SZ;
         const N3 x = nb3(s);
         const int self = x.self;
         real v0[4], v1[4], v2[4], v3[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          v0[f] = at(self + BQ + f * PQ);
+          v0[f] = (BBW_CARRY & 1) ? qcur[f][s < S3N ? s : 0] : at(self + BQ + f * PQ);
           v1[f] = at(x.up[0] + BQ + f * PQ);
           v2[f] = at(x.up[1] + BQ + f * PQ);
           v3[f] = at(x.up[2] + BQ + f * PQ);
@@ -480,14 +548,17 @@ void stage_kernel(const StageArgs<real> a) {
         real gr[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          const real G0 = at(gm + (3 * i) * SZ), G1 = at(gm + (3 * i + 1) * SZ), G2 = at(gm + (3 * i + 2) * SZ);
+          const real G0 = geo_at(e, 3 * i), G1 = geo_at(e, 3 * i + 1), G2 = geo_at(e, 3 * i + 2);
           gr[i] = -half_n * (G0 * (v1[0] - v0[0]) + G1 * (v2[0] - v0[0]) + G2 * (v3[0] - v0[0]));
           dv += G0 * (v1[1 + i] - v0[1 + i]) + G1 * (v2[1 + i] - v0[1 + i]) + G2 * (v3[1 + i] - v0[1 + i]);
         }
-        at(self + BA + 0 * PY) = gr[0];
-        at(self + BA + 1 * PY) = gr[1];
-        at(self + BA + 2 * PY) = gr[2];
-        at(self + BA + 3 * PY) = -half_n * dv;
+        const int sn = s < S3N ? s : 0;
+        ycar[0][sn] = gr[0];
+        ycar[1][sn] = gr[1];
+        ycar[2][sn] = gr[2];
+        ycar[3][sn] = -half_n * dv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) at(self + BA + c * PY) = ycar[c][sn];
       }
     }
     team_sync();
@@ -505,7 +576,7 @@ void stage_kernel(const StageArgs<real> a) {
       real t[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        t[c] = w0 * at(self + BA + c * PY) + w1 * at(x.dn[0] + BA + c * PY) + w2 * at(x.dn[1] + BA + c * PY) +
+        t[c] = w0 * ((BBW_CARRY & 2) ? ycar[c][s] : at(self + BA + c * PY)) + w1 * at(x.dn[0] + BA + c * PY) + w2 * at(x.dn[1] + BA + c * PY) +
                w3 * at(x.dn[2] + BA + c * PY);
       acc[0][s] = t[3];
       acc[1][s] = t[0];
@@ -527,29 +598,18 @@ void stage_kernel(const StageArgs<real> a) {
                    wm = at(fown[u] + BQ + 3 * PQ);
         const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
         const real nx = at(gf + SZ), ny = at(gf + 2 * SZ), nz = at(gf + 3 * SZ);
-        real pp, up, vp, wp;
-        if (cur_conn[u] >= 0) {
-          pp = nb[0][u];
-          up = nb[1][u];
-          vp = nb[2][u];
-          wp = nb[3][u];
-        } else if (a.bc == 0) {  // p = 0 wall: p+ = -p, u+ = u
-          pp = -pm;
-          up = um;
-          vp = vm;
-          wp = wm;
-        } else {  // rigid wall: p+ = p, u+ = u - 2 (u.n) n
-          const real un = um * nx + vm * ny + wm * nz;
-          pp = pm;
-          up = um - 2 * un * nx;
-          vp = vm - 2 * un * ny;
-          wp = wm - 2 * un * nz;
-        }
-        const real jp = pp - pm;
-        const real jun = (up - um) * nx + (vp - vm) * ny + (wp - wm) * nz;
-        const int dst = wb + BF + (m * CHP + fe) * SZ;
-        at(dst) = real(0.5) * (a.tau_p * jp - jun);
-        at(dst + 4 * EW * SZ) = real(0.5) * (a.tau_u * jun - jp);
+        // jumps [[p]] = p+ - p and [[u]].n against the neighbour, or against the mirror
+        // state on a wall: p = 0 walls take p+ = -p, u+ = u; rigid walls p+ = p,
+        // u+ = u - 2 (u.n) n, so [[u]].n = -2 u.n (unit normals)
+        const real jp_in = nb[0][u] - pm;
+        const real jun_in = (nb[1][u] - um) * nx + (nb[2][u] - vm) * ny + (nb[3][u] - wm) * nz;
+        const real jp_wall = a.bc == 0 ? real(-2) * pm : real(0);
+        const real jun_wall = a.bc == 0 ? real(0) : real(-2) * (um * nx + vm * ny + wm * nz);
+        const bool interior = cur_conn[u] >= 0;
+        const real jp = interior ? jp_in : jp_wall;
+        const real jun = interior ? jun_in : jun_wall;
+        at(wb + BF + L::cunit(m, fe) * SZ) = real(0.5) * (a.tau_p * jp - jun);
+        at(wb + BF + L::cunit(m, fe + 4 * EW) * SZ) = real(0.5) * (a.tau_u * jun - jp);
       }
     }
     // the RK register of this group: issued now, consumed by the update at the end
@@ -559,22 +619,27 @@ void stage_kernel(const StageArgs<real> a) {
       const int item = lane + TL * s;
       const int e = item - (item / EW) * EW, pos = item / EW;
       const bool ok = item < EW * NP && k0 + e < K;
+      const size_t idx = ok ? (size_t)(k0 + e) * NP + pos : (size_t)k0 * NP;  // see the prefetch
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        if constexpr (UPDATE) rs[f][s] = ok ? a.res[((size_t)f * K + k0 + e) * NP + pos] : real(0);
+        if constexpr (UPDATE) rs[f][s] = a.res[(size_t)f * K * NP + idx];
         else rs[f][s] = real(0);
       }
     }
     team_sync();
 
     // ---- lift: L_0 on each face flux, then the layer chain (levels pre-scaled by l_i) -----
+    real ccar[S2];  // the lane's own face-chain value of the previous lift phase
+#pragma unroll
+    for (int t = 0; t < S2; ++t) ccar[t] = real(0);
 #pragma unroll
     for (int t = 0; t < S2; ++t) {  // T = (E^N_{N-1})^T F
       const int item = lane + TL * t;
       if (t * TL < CH * NFP1 && item < CH * NFP1) {
         const N2 x = nb2(t);
-        at(x.self + BT) = inv_n * (real(N - x.tb) * at(x.self + BF) + real(x.b1 + 1) * at(x.up[0] + BF) +
-                                   real(x.b2 + 1) * at(x.up[1] + BF));
+        ccar[t] = inv_n * (real(N - x.tb) * at(x.self + BF) + real(x.b1 + 1) * at(x.up[0] + BF) +
+                           real(x.b2 + 1) * at(x.up[1] + BF));
+        at(x.self + BT) = ccar[t];
       }
     }
     team_sync();
@@ -587,9 +652,9 @@ void stage_kernel(const StageArgs<real> a) {
         const int item = lane + TL * t;
         if (item < CH * NFP) {
           const N2 x = nb2(t);
-          const real et =
-              real(N - x.tb) * at(x.self + BT) + real(x.b1) * at(x.dn[0] + BT) + real(x.b2) * at(x.dn[1] + BT);
-          at(x.self + BC) = l0a * at(x.self + BF) + l0b * et;
+          const real et = real(N - x.tb) * ((BBW_CARRY & 4) ? ccar[t] : at(x.self + BT)) + real(x.b1) * at(x.dn[0] + BT) + real(x.b2) * at(x.dn[1] + BT);
+          ccar[t] = l0a * at(x.self + BF) + l0b * et;
+          at(x.self + BC) = ccar[t];
         }
       }
     }
@@ -605,8 +670,9 @@ void stage_kernel(const StageArgs<real> a) {
         const int item = lane + TL * t;
         if (t * TL < cnt && item < cnt) {
           const N2 x = nb2(t);
-          at(x.self + dst) = sc * (real(n - x.tb) * at(x.self + src) + real(x.b1 + 1) * at(x.up[0] + src) +
-                                   real(x.b2 + 1) * at(x.up[1] + src));
+          ccar[t] = sc * (real(n - x.tb) * ((BBW_CARRY & 4) ? ccar[t] : at(x.self + src)) + real(x.b1 + 1) * at(x.up[0] + src) +
+                          real(x.b2 + 1) * at(x.up[1] + src));
+          at(x.self + dst) = ccar[t];
         }
       }
       team_sync();
@@ -620,20 +686,23 @@ void stage_kernel(const StageArgs<real> a) {
         const int e = item - (item / EW) * EW;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          const int gf = wb + BP + (e * 25 + 9 + 4 * f) * SZ;
           const int lpf = lpo[s][f];
-          const real sc = at(gf);
+          const real sc = geo_at(e, 9 + 4 * f);
           const real lpv = at(lpf + BC);
-          const real luv = at(lpf + BC + 4 * EW * SZ) * sc;
+          // the u channel (channel + 4 EW) of the same row: with a swizzle and 4 EW < 8 it
+          // is the slot with bit 2 flipped (rows are 8-real aligned), else a fixed offset
+          constexpr bool flip = L::SWZ && (4 * EW) % 8 != 0;
+          const int lpu = flip ? ((lpf + BC) ^ (4 * SZ)) : (lpf + BC + 4 * EW * SZ);
+          const real luv = at(lpu) * sc;
           acc[0][s] += sc * lpv;
-          acc[1][s] += at(gf + SZ) * luv;
-          acc[2][s] += at(gf + 2 * SZ) * luv;
-          acc[3][s] += at(gf + 3 * SZ) * luv;
+          acc[1][s] += geo_at(e, 10 + 4 * f) * luv;
+          acc[2][s] += geo_at(e, 11 + 4 * f) * luv;
+          acc[3][s] += geo_at(e, 12 + 4 * f) * luv;
         }
         if constexpr (M > 0) {
           at(wb + BR + item * SZ) = acc[0][s] * fac3[s];
         } else {
-          acc[0][s] *= at(wb + BP + (25 * EW + e * MP) * SZ);
+          acc[0][s] *= c2_at(e, 0);
         }
       }
     }
@@ -643,18 +712,22 @@ void stage_kernel(const StageArgs<real> a) {
       team_sync();
       constexpr int NH1 = L::NH1;
       constexpr int BH = BB, BH1 = BB + EW * NH * SZ, BL = BH1 + EW * NH1 * SZ;
+      real wcar[S3];  // the lane's own value of the previous WADG phase
+#pragma unroll
+      for (int s = 0; s < S3; ++s) wcar[s] = real(0);
+      // re-zero the guards in front of levels 1..N (the face chain shared this space)
+      if (lane < N * EW) at(wb + BL + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
 #pragma unroll
       for (int s = 0; s < S3; ++s) {
         const int item = lane + TL * s;
         if (item < EW * NH) {
           const int e = item - (item / EW) * EW;
-          const int c2s = wb + BP + (25 * EW + e * MP) * SZ;
           real h = 0;
           if constexpr (L::MUL_REGS) {
 #pragma unroll
             for (int b = 0; b < MP; ++b) {
               const int off = (b % 2 == 0) ? (mpos[s][b / 2] & 0xFFFF) : ((unsigned)mpos[s][b / 2] >> 16);
-              h += at(off) * at(c2s + b * SZ);
+              h += at(off) * c2_at(e, b);
             }
           } else {
             const int pp = opq(pa3[s]);
@@ -670,11 +743,12 @@ void stage_kernel(const StageArgs<real> a) {
                   const int b1 = sb - b2 - b3, b0 = M - sb;
                   const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0 >= b0;
                   const int p = wb + (ok ? BR + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
-                  h += at(p) * at(c2s + b * SZ);
+                  h += at(p) * c2_at(e, b);
                   ++b;
                 }
           }
-          at(wb + BH + item * SZ) = h * facH[s];
+          wcar[s] = h * facH[s];
+          at(wb + BH + item * SZ) = wcar[s];
         }
       }
       team_sync();
@@ -690,8 +764,9 @@ void stage_kernel(const StageArgs<real> a) {
           const int item = lane + TL * s;
           if (s * TL < cnt && item < cnt) {
             const N3 x = nb3(s);
-            at(x.self + dst) = inv * (real(n - x.sa) * at(x.self + src) + real(x.a1 + 1) * at(x.up[0] + src) +
-                                      real(x.a2 + 1) * at(x.up[1] + src) + real(x.a3 + 1) * at(x.up[2] + src));
+            const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + src);
+            wcar[s] = inv * (real(n - x.sa) * self_v + (at(x.up[0] + src) + at(x.up[1] + src) + at(x.up[2] + src)));
+            at(x.self + dst) = wcar[s];
           }
         }
         team_sync();
@@ -708,14 +783,20 @@ void stage_kernel(const StageArgs<real> a) {
           const int item = lane + TL * s;
           if (s * TL < cnt && item < cnt) {
             const N3 x = nb3(s);
-            at(x.self + dst) = inv * (real(n - x.sa) * at(x.self + src) + real(x.a1 + 1) * at(x.up[0] + src) +
-                                      real(x.a2 + 1) * at(x.up[1] + src) + real(x.a3 + 1) * at(x.up[2] + src));
+            const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + src);
+            wcar[s] = inv * (real(n - x.sa) * self_v + (at(x.up[0] + src) + at(x.up[1] + src) + at(x.up[2] + src)));
+            at(x.self + dst) = wcar[s];
           }
         }
         team_sync();
       }
-      // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}
-      if (lane < EW) at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) *= a.cj[N];
+      // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}. The
+      // reductions above kept A(alpha) x (one weight, n - |a|, on the e0 term); here s is
+      // kept as s / A(alpha), so r enters with 1/A^2 and the elevation again has one weight.
+      if (lane < EW) {
+        wcar[0] *= a.cj[N];
+        at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) = wcar[0];
+      }
       team_sync();
 #pragma unroll
       for (int j = N - 1; j >= 0; --j) {
@@ -729,9 +810,10 @@ void stage_kernel(const StageArgs<real> a) {
           const int item = lane + TL * s;
           if (s * TL < cnt && item < cnt) {
             const N3 x = nb3(s);
-            const real el = real(n - x.sa) * at(x.self + hi) + real(x.a1) * at(x.dn[0] + hi) +
-                            real(x.a2) * at(x.dn[1] + hi) + real(x.a3) * at(x.dn[2] + hi);
-            at(x.self + lo) = cj * at(x.self + lo) + inv * el;
+            const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + hi);
+            const real el = real(n - x.sa) * self_v + (at(x.dn[0] + hi) + at(x.dn[1] + hi) + at(x.dn[2] + hi));
+            wcar[s] = (cj * iA2[s]) * at(x.self + lo) + inv * el;
+            at(x.self + lo) = wcar[s];
           }
         }
         team_sync();
@@ -739,7 +821,7 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
       for (int s = 0; s < S3N; ++s) {
         const int item = lane + TL * s;
-        if (item < EW * NP) acc[0][s] = at(wb + BL + item * SZ);
+        if (item < EW * NP) acc[0][s] = aF[s] * wcar[s];
       }
     }
 
