@@ -136,6 +136,45 @@ def cpu_baseline(dt, steps):
             "sample": f"cube 16^3x6 = {K} tets, N={N}, M={M}, same medium and pulse, {steps} LSRK4 steps, FP64"}
 
 
+def c3_sweep(steps, warmup):
+    """The 196,608-tet mesh at N = 4..9, M = N/2, three-layer medium (c^2 in {1, 2, 4}, seed 1)
+    projected to P^M, Gaussian pulse: FP64 and FP32 throughput and per-field FP32-vs-FP64
+    relative L2 after warmup + steps LSRK4 steps (both legs share the c^2_M data)."""
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from workloads import c2_three_layer, ic_gaussian_pulse, kuhn_cube_mesh
+    xyz, etov = kuhn_cube_mesh(CELLS)
+    out = []
+    for n in range(4, 10):
+        m = n // 2
+        s64 = bb.Solver(xyz, etov, n, m, dtype="f64")
+        c2 = s64.project_c2(c2_three_layer(1))
+        q0 = np.zeros((4, s64.K, s64.Np))
+        q0[0] = s64.project_function(ic_gaussian_pulse, n)
+        dt = s64.suggest_dt(0.5)
+        q64, ms64, _, copy64 = run_leg(s64, q0, dt, steps, warmup)
+        s32 = bb.Solver(xyz, etov, n, m, dtype="f32")
+        s32.set_c2(c2)
+        q32, ms32, _, copy32 = run_leg(s32, q0, dt, steps, warmup)
+        diff = (q32.double() - q64).contiguous()
+        rel = np.sqrt(s64.l2norm2(diff) / np.maximum(s64.l2norm2(q64), 1e-300)).tolist()
+        dofs = s64.K * s64.Np * 4
+        entry = {"N": n, "M": m, "dofs": dofs, "dt": dt}
+        for tag, ms, cp, word in (("f64", ms64, copy64, 8), ("f32", ms32, copy32, 4)):
+            kms = (ms - cp) / (5 * steps)
+            entry[tag] = {"gdof_updates_per_s": dofs * steps / (ms * 1e-3) / 1e9, "ms_per_step": ms / steps,
+                          "kernel_ms": kms,
+                          "alg_frac_hbm": algorithmic_bytes_per_element(n, m, word) * s64.K / (kms * 1e-3) / 1e9
+                          / HBM_PEAK_GBS}
+        entry["fp32_rel_l2_vs_fp64_per_field"] = rel
+        out.append(entry)
+        print(json.dumps({"c3_progress": entry}), file=sys.stderr, flush=True)
+        del s64, s32, q64, q32, diff
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +186,8 @@ def main():
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     ap.add_argument("--cpu-steps", type=int, default=15, help="LSRK4 steps of the CPU oracle sample")
+    ap.add_argument("--c3", action="store_true",
+                    help="instead of the default workload: N = 4..9, M = N/2 on the three-layer medium, FP64 and FP32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -157,6 +198,12 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.c3:
+        res = c3_sweep(args.steps, args.warmup)
+        print(json.dumps({"metric": "GDOF-updates/s per RK step (FP32 vs FP64) + % HBM peak, at stated L2 error",
+                          "unit": "GDOF-updates/s", "workload": "cube196k_N4-9_three_layer", "steps": args.steps,
+                          "warmup": args.warmup, "data": "synthetic", "c3": res}), flush=True)
+        return
 
     out = {}
     s64, q0 = setup("f32" if args.fp32_only else "f64")
