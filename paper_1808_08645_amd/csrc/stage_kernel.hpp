@@ -229,6 +229,12 @@ void stage_kernel(const StageArgs<real> a) {
   constexpr int BZ = L::OFF_Z * SZ;
   constexpr int PQ = L::PLQ * SZ, PY = L::PLY * SZ;  // plane strides
   __shared__ __attribute__((aligned(16))) real smem[TPB * L::TOTAL];
+  // Without product positions in registers, a block-wide table holds pos(gamma - beta) for
+  // every beta and product item (one byte each; NP marks a term that does not exist and
+  // reads the zero cell after R).
+  constexpr int PTAB = L::MUL_REGS ? 1 : MP * EW * NH;
+  __shared__ uint8_t ptab[PTAB];
+  static_assert(L::MUL_REGS || NP < 256, "positions must fit a byte");
   char* const lds = reinterpret_cast<char*>(smem);
   auto at = [lds](int byteoff) -> real& { return *reinterpret_cast<real*>(lds + byteoff); };
 
@@ -421,6 +427,18 @@ void stage_kernel(const StageArgs<real> a) {
 
   // zero this wave's LDS slice once (stale reads are weighted by zero and must be finite)
   for (int i = lane; i < L::TOTAL; i += TL) at(wb + i * SZ) = real(0);
+  if constexpr (!L::MUL_REGS) {
+    for (int i = threadIdx.x; i < PTAB; i += blockDim.x) {
+      const int b = i / (EW * NH), item = i - b * (EW * NH), pos = item / EW;
+      int a1, a2, a3, b1, b2, b3;
+      pos3(pos, a1, a2, a3);
+      pos3(b, b1, b2, b3);
+      const int a0 = N + M - a1 - a2 - a3, b0 = M - b1 - b2 - b3;
+      const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0 >= b0;
+      ptab[i] = (uint8_t)(ok ? g3(a1 - b1, a2 - b2, a3 - b3) : NP);
+    }
+    __syncthreads();
+  }
   team_sync();
 
   // ---- prefetch of the next element group ------------------------------------------------
@@ -701,6 +719,8 @@ void stage_kernel(const StageArgs<real> a) {
         }
         if constexpr (M > 0) {
           at(wb + BR + item * SZ) = acc[0][s] * fac3[s];
+          if constexpr (!L::MUL_REGS)
+            if (s == 0 && lane < EW) at(wb + BR + (NP * EW + lane) * SZ) = real(0);  // the zero cell
         } else {
           acc[0][s] *= c2_at(e, 0);
         }
@@ -717,37 +737,50 @@ void stage_kernel(const StageArgs<real> a) {
       for (int s = 0; s < S3; ++s) wcar[s] = real(0);
       // re-zero the guards in front of levels 1..N (the face chain shared this space)
       if (lane < N * EW) at(wb + BL + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
+      // h_gamma = sum_beta R_{gamma-beta} c2_beta/beta!
+      real h[S3];
+#pragma unroll
+      for (int s = 0; s < S3; ++s) h[s] = real(0);
+      if constexpr (L::MUL_REGS) {  // few terms: positions in registers, slot by slot
+#pragma unroll
+        for (int s = 0; s < S3; ++s) {
+          const int item = lane + TL * s;
+          if (item < EW * NH) {
+            const int e = item - (item / EW) * EW;
+#pragma unroll
+            for (int b = 0; b < MP; ++b) {
+              const int off = (b % 2 == 0) ? (mpos[s][b / 2] & 0xFFFF) : ((unsigned)mpos[s][b / 2] >> 16);
+              h[s] += at(off) * c2_at(e, b);
+            }
+          }
+        }
+      } else {  // many terms: positions from the table, beta outermost so that one c^2
+                // coefficient is live at a time (a one-element team reads it once)
+        int b = 0;
+#pragma unroll
+        for (int sb = 0; sb <= M; ++sb)
+#pragma unroll
+          for (int b3 = 0; b3 <= sb; ++b3)
+#pragma unroll
+            for (int b2 = 0; b2 <= sb - b3; ++b2) {
+              const real cb = c2_at(0, b);
+#pragma unroll
+              for (int s = 0; s < S3; ++s) {
+                const int item = lane + TL * s;
+                if (s * TL < EW * NH && item < EW * NH) {
+                  const int e = item - (item / EW) * EW;
+                  const int off = wb + BR + ((int)ptab[b * (EW * NH) + item] * EW + e) * SZ;
+                  h[s] += at(off) * (EW == 1 ? cb : c2_at(e, b));
+                }
+              }
+              ++b;
+            }
+      }
 #pragma unroll
       for (int s = 0; s < S3; ++s) {
         const int item = lane + TL * s;
         if (item < EW * NH) {
-          const int e = item - (item / EW) * EW;
-          real h = 0;
-          if constexpr (L::MUL_REGS) {
-#pragma unroll
-            for (int b = 0; b < MP; ++b) {
-              const int off = (b % 2 == 0) ? (mpos[s][b / 2] & 0xFFFF) : ((unsigned)mpos[s][b / 2] >> 16);
-              h += at(off) * c2_at(e, b);
-            }
-          } else {
-            const int pp = opq(pa3[s]);
-            const int a1 = pp & 255, a2 = (pp >> 8) & 255, a3 = (pp >> 16) & 255, sa = pp >> 24;
-            const int a0 = N + M - sa;
-            int b = 0;  // beta in the graded coefficient order of c^2
-#pragma unroll
-            for (int sb = 0; sb <= M; ++sb)
-#pragma unroll
-              for (int b3 = 0; b3 <= sb; ++b3)
-#pragma unroll
-                for (int b2 = 0; b2 <= sb - b3; ++b2) {
-                  const int b1 = sb - b2 - b3, b0 = M - sb;
-                  const bool ok = a1 >= b1 && a2 >= b2 && a3 >= b3 && a0 >= b0;
-                  const int p = wb + (ok ? BR + (g3(a1 - b1, a2 - b2, a3 - b3) * EW + e) * SZ : BZ);
-                  h += at(p) * c2_at(e, b);
-                  ++b;
-                }
-          }
-          wcar[s] = h * facH[s];
+          wcar[s] = h[s] * facH[s];
           at(wb + BH + item * SZ) = wcar[s];
         }
       }
