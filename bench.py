@@ -175,6 +175,65 @@ def c3_sweep(steps, warmup):
     return out
 
 
+def wadg_compare(n_list, m_list, reps):
+    """Dense quadrature WADG (matrix cores) against the Bernstein update on the 196,608-tet mesh:
+    times of the fused Bernstein right-hand side, the plain DG right-hand side (c^2 = 1, no
+    weight adjustment), and the dense update alone, with c^2_M of the bump medium at the points."""
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from workloads import kuhn_cube_mesh
+    xyz, etov = kuhn_cube_mesh(CELLS)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = []
+    for n in n_list:
+        # the plain DG right-hand side: the fused kernel with M = 0 and c^2 = 1
+        s0 = bb.Solver(xyz, etov, n, 0, dtype="f64")
+        s0.set_c2(np.ones((s0.K, 1)))
+        q0 = s0.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s0.K, s0.Np)))
+        r0 = torch.empty_like(q0)
+        t_dg = timed(lambda: s0.rhs(q0, r0))
+        del s0, q0, r0
+        for m in m_list:
+            if m > n:
+                continue
+            s = bb.Solver(xyz, etov, n, m, dtype="f64")
+            s.project_c2(c2_bumps_medium())
+            s.dense_set_c2(None)
+            q = s.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s.K, s.Np)))
+            r = torch.empty_like(q)
+            t_bb = timed(lambda: s.rhs(q, r))
+            t_dense_rhs = timed(lambda: s.rhs_dense(q, r))
+            p0 = q[0].contiguous()
+            p1 = torch.empty_like(p0)
+            t_dense = timed(lambda: s.dense_update(p0, p1))
+            e = {"N": n, "M": m, "Np": s.Np, "nq_dense": s.dense_npoints(), "rhs_bernstein_ms": t_bb,
+                 "rhs_dense_ms": t_dense_rhs, "dense_update_ms": t_dense, "plain_dg_rhs_ms": t_dg,
+                 "bernstein_update_ms": t_bb - t_dg,
+                 "dense_update_tflops": 4.0 * s.dense_npoints() * s.Np * s.K / (t_dense * 1e-3) / 1e12}
+            out.append(e)
+            print(json.dumps({"wadg_compare_progress": e}), file=sys.stderr, flush=True)
+            del s, q, r, p0, p1
+            torch.cuda.empty_cache()
+    return out
+
+
+def c2_bumps_medium():
+    from workloads import c2_gaussian_bumps
+    return c2_gaussian_bumps(0)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +245,8 @@ def main():
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter reference)")
     ap.add_argument("--cpu-steps", type=int, default=15, help="LSRK4 steps of the CPU oracle sample")
+    ap.add_argument("--wadg-compare", action="store_true",
+                    help="instead of the default workload: dense quadrature WADG vs the Bernstein update, N = 2..9")
     ap.add_argument("--c3", action="store_true",
                     help="instead of the default workload: N = 4..9, M = N/2 on the three-layer medium, FP64 and FP32")
     args = ap.parse_args()
@@ -198,6 +259,11 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.wadg_compare:
+        res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
+        print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
+                          "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
+        return
     if args.c3:
         res = c3_sweep(args.steps, args.warmup)
         print(json.dumps({"metric": "GDOF-updates/s per RK step (FP32 vs FP64) + % HBM peak, at stated L2 error",

@@ -200,6 +200,35 @@ int bbwadg_energy(bbwadg_ctx* ctx, const void* q, int64_t k0, int64_t k1, double
 int bbwadg_project_fn(bbwadg_ctx* ctx, double (*fn)(double x, double y, double z, void* user),
                       void* user, int32_t field, void* q_out, void* stream);
 
+/* ---- dense quadrature WADG: the comparison baseline (paper Section 3.3, eq. pwadg) ----
+ * dp/dt = P_q diag(c^2(x_q)) V_q r_p with V_q the degree-N Bernstein basis at the points of
+ * the collapsed Gauss-Jacobi rule with n = floor((2N+M+2)/2) points per direction (exact to
+ * degree 2N+M) and P_q = M^{-1} V_q^T W, applied as dense products on the FP64 matrix cores.
+ * With c^2_M at the points it equals the fast Bernstein update (paper Theorem 5.1); with the
+ * true c^2 at the points it is the quadrature WADG the paper compares against. FP64 device
+ * contexts only (EINVAL otherwise). The point values take K * 16 ceil(nq/16) doubles of
+ * device memory, allocated by the first bbwadg_dense_set_c2 together with the tables. */
+
+/* Points of the dense rule per element (nq = n^3). */
+int bbwadg_dense_npoints(const bbwadg_ctx* ctx, int64_t* nq);
+
+/* Physical points of the dense rule for elements [k0, k1): host [k1-k0][nq][3]. */
+int bbwadg_dense_points(const bbwadg_ctx* ctx, int64_t k0, int64_t k1, double* xyz_out);
+
+/* Set c^2 at the dense points: host FP64 [K][nq] (in bbwadg_dense_points' order), or NULL to
+ * evaluate the stored c^2_M there. EC2 if a value is not finite and positive, or if c2q is
+ * NULL and no c^2_M is set. Synchronises `stream`. */
+int bbwadg_dense_set_c2(bbwadg_ctx* ctx, const double* c2q, void* stream);
+
+/* The dense update alone: out[k] = P_q diag(c^2 at element k's points) V_q r[k] for device
+ * FP64 arrays r, out [K][Np] (they may be the same array). EC2 before bbwadg_dense_set_c2. */
+int bbwadg_dense_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
+
+/* Right-hand side with the dense update in place of the Bernstein one: the plain DG
+ * right-hand side (volume, fluxes and lift as in bbwadg_rhs, with c^2 = 1) followed by
+ * bbwadg_dense_update on the p field. q, rhs: device [4][K][Np] FP64, must not overlap. */
+int bbwadg_rhs_dense(bbwadg_ctx* ctx, const void* q, void* rhs, double t, void* stream);
+
 /* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
  * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
  * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */

@@ -28,6 +28,8 @@ EXPORTS = (
     "bbwadg_projection_points", "bbwadg_project_samples", "bbwadg_project_c2",
     "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
     "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
+    "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
+    "bbwadg_rhs_dense",
     "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
@@ -90,6 +92,11 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_energy": (C.c_int, [vp, vp, i64, i64, pd, vp]),
         "bbwadg_project_fn": (C.c_int, [vp, C2_CALLBACK, vp, i32, vp, vp]),
         "bbwadg_coef_index": (C.c_int32, [i32, i32, i32]),
+        "bbwadg_dense_npoints": (C.c_int, [vp, pi64]),
+        "bbwadg_dense_points": (C.c_int, [vp, i64, i64, pd]),
+        "bbwadg_dense_set_c2": (C.c_int, [vp, vp, vp]),
+        "bbwadg_dense_update": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_rhs_dense": (C.c_int, [vp, vp, vp, dbl, vp]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }
@@ -357,4 +364,51 @@ class Solver:
         k1 = self.K if k1 is None else k1
         out = np.zeros(4)
         _check(self._lib.bbwadg_energy(self._ctx, C.c_void_p(q.data_ptr()), k0, k1, _dptr(out), self._stream()))
+        return out
+
+    # ------------------------------------------------- dense quadrature WADG (baseline)
+    def dense_npoints(self) -> int:
+        n = C.c_int64()
+        _check(self._lib.bbwadg_dense_npoints(self._ctx, C.byref(n)))
+        return n.value
+
+    def dense_points(self, k0: int = 0, k1: int | None = None) -> np.ndarray:
+        k1 = self.K if k1 is None else k1
+        out = np.empty((k1 - k0, self.dense_npoints(), 3))
+        _check(self._lib.bbwadg_dense_points(self._ctx, k0, k1, _dptr(out)))
+        return out
+
+    def dense_set_c2(self, fn=None, chunk: int = 8192):
+        """c^2 at the dense points: None evaluates the stored c^2_M; a vectorised fn(x, y, z)
+        gives the quadrature WADG of the true wavespeed."""
+        if fn is None:
+            _check(self._lib.bbwadg_dense_set_c2(self._ctx, None, self._stream()))
+            return
+        nq = self.dense_npoints()
+        vals = np.empty((self.K, nq))
+        for a in range(0, self.K, chunk):
+            b = min(self.K, a + chunk)
+            X = self.dense_points(a, b)
+            vals[a:b] = np.broadcast_to(np.asarray(fn(X[..., 0], X[..., 1], X[..., 2]), dtype=np.float64), X.shape[:2])
+        _check(self._lib.bbwadg_dense_set_c2(self._ctx, C.c_void_p(vals.ctypes.data), self._stream()))
+
+    def dense_update(self, r, out=None):
+        """out[k] = P_q diag(c^2) V_q r[k] for device float64 arrays of shape (K, Np)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(r)
+        for t, name in ((r, "r"), (out, "out")):
+            if not (t.is_cuda and t.dtype == torch.float64 and tuple(t.shape) == (self.K, self.Np) and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape ({self.K}, {self.Np})")
+        _check(self._lib.bbwadg_dense_update(self._ctx, C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
+                                             self._stream()))
+        return out
+
+    def rhs_dense(self, q, out=None, t: float = 0.0):
+        self._check_state(q, "q")
+        if out is None:
+            out = self.empty_state()
+        self._check_state(out, "out")
+        _check(self._lib.bbwadg_rhs_dense(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          float(t), self._stream()))
         return out

@@ -59,6 +59,22 @@ struct QuadReduceArgs {
   int32_t Np, Mp, nq;
 };
 int quad_reduce_blocks(int64_t nelems, int max_blocks);
+
+// Dense quadrature WADG update out = P_q diag(c2q) V_q r (FP64), tables in MFMA operand order:
+// va[qc][ks][lane] = V_q[16 qc + lane%16][4 ks + lane/16] (NQP/16 x NPP/4 x 64) and
+// pa[qc][t][ks][lane] = P_q[16 t + lane%16][16 qc + 4 ks + lane/16] (NQP/16 x NPP/16 x 4 x 64),
+// zero-padded to NPP = 16 ceil(Np/16) and NQP = 16 ceil(Nq/16).
+struct DenseArgs {
+  const double* r;    // [K][Np] input coefficients
+  double* out;        // [K][Np] result (may alias r: each tile stages its inputs first)
+  const double* va;
+  const double* pa;
+  const double* c2q;  // [K][nqp] c^2 at the points (padding zero)
+  int64_t K;
+  int32_t nqc;        // NQP / 16
+  int32_t nqp;        // NQP
+};
+int launch_wadg_dense(int N, const DenseArgs& a, void* stream);
 int launch_quad_reduce(int dtype, int mode, const QuadReduceArgs& a, int nblocks, void* stream);
 
 }  // namespace bbw

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -179,8 +180,8 @@ struct Projector {
   std::vector<std::array<ld, 4>> lam;
 };
 
-void build_projector(int d, Projector& pr) {
-  int n = d + 3;
+// Projection onto degree d with the collapsed rule of n points per direction.
+void build_projector_rule(int d, int n, Projector& pr) {
   std::vector<ld> w;
   tet_rule(n, pr.lam, w);
   int nq = (int)w.size();
@@ -224,6 +225,8 @@ void build_projector(int d, Projector& pr) {
   pr.degree = d;
   pr.nq = nq;
 }
+
+void build_projector(int d, Projector& pr) { build_projector_rule(d, d + 3, pr); }
 
 // ------------------------------------------------------------------------ tables
 // The stage kernel derives all its index maps from the graded coefficient order; the
@@ -274,6 +277,14 @@ struct bbwadg_ctx {
   void* d_rbasis_c2 = nullptr;  // [Mp][nq] B^M
   void* d_rw = nullptr;         // [nq]
   int nq_red = 0;
+  // dense quadrature WADG (comparison baseline)
+  Projector dense;              // degree N at the dense rule: B = V_q, P = P_q
+  int dense_n = 0, dense_nqp = 0;
+  void* d_dva = nullptr;        // V_q in MFMA operand order
+  void* d_dpa = nullptr;        // P_q in MFMA operand order
+  void* d_c2q = nullptr;        // [K][dense_nqp] c^2 at the dense points
+  void* d_ones = nullptr;       // [K] ones: c^2 = 1 for the plain DG right-hand side
+  bool c2q_set = false;
 };
 
 namespace {
@@ -300,8 +311,9 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 }
 
 void free_device(bbwadg_ctx* c) {
-  void** ptrs[] = {&c->d_geo,     &c->d_conn,   &c->d_c2,         &c->d_c2k, &c->d_q2, &c->d_J,
-                   &c->d_mass,    &c->d_partial, &c->d_rbasis, &c->d_rbasis_c2, &c->d_rw};
+  void** ptrs[] = {&c->d_geo,     &c->d_conn,    &c->d_c2,         &c->d_c2k, &c->d_q2,
+                   &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
+                   &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -454,6 +466,56 @@ int quad_reduce(bbwadg_ctx* c, int mode, const void* q, int64_t k0, int64_t k1, 
     out[f] = acc;
   }
   return 0;
+}
+
+// Points per direction of the dense WADG rule: exact for degree 2N+M, so that with c^2_M
+// at the points the dense update is the exact projection (the fast method's result).
+int dense_rule_n(const bbwadg_ctx* c) { return (2 * c->N + c->M + 2) / 2; }
+
+const Projector& get_dense(bbwadg_ctx* c) {
+  const int n = dense_rule_n(c);
+  if (c->dense_n != n) {
+    build_projector_rule(c->N, n, c->dense);
+    c->dense_n = n;
+    c->dense_nqp = (c->dense.nq + 15) / 16 * 16;
+  }
+  return c->dense;
+}
+
+// Upload V_q and P_q in MFMA operand order (zero padded), once.
+int dense_tables(bbwadg_ctx* c) {
+  if (c->d_dva) return 0;
+  const Projector& pr = get_dense(c);
+  const int np = c->Np, nq = pr.nq, npp = (np + 15) / 16 * 16, nqp = c->dense_nqp;
+  const int nqc = nqp / 16, nk = npp / 4, nt = npp / 16;
+  std::vector<double> va((size_t)nqc * nk * 64, 0.0), pa((size_t)nqc * nt * 4 * 64, 0.0);
+  for (int qc = 0; qc < nqc; ++qc)
+    for (int l = 0; l < 64; ++l) {
+      for (int ks = 0; ks < nk; ++ks) {
+        const int q = 16 * qc + l % 16, i = 4 * ks + l / 16;
+        va[((size_t)qc * nk + ks) * 64 + l] = (q < nq && i < np) ? pr.B[(size_t)q * np + i] : 0.0;
+      }
+      for (int t = 0; t < nt; ++t)
+        for (int ks = 0; ks < 4; ++ks) {
+          const int i = 16 * t + l % 16, q = 16 * qc + 4 * ks + l / 16;
+          pa[(((size_t)qc * nt + t) * 4 + ks) * 64 + l] = (q < nq && i < np) ? pr.P[(size_t)i * nq + q] : 0.0;
+        }
+    }
+  std::vector<double> ones((size_t)c->K, 1.0);
+  int rc = dmalloc(&c->d_dva, va.size() * 8);
+  if (!rc) rc = dmalloc(&c->d_dpa, pa.size() * 8);
+  if (!rc) rc = dmalloc(&c->d_ones, ones.size() * 8);
+  if (!rc) rc = upload(c->d_dva, va.data(), va.size() * 8);
+  if (!rc) rc = upload(c->d_dpa, pa.data(), pa.size() * 8);
+  if (!rc) rc = upload(c->d_ones, ones.data(), ones.size() * 8);
+  if (rc) {
+    void** ptrs[] = {&c->d_dva, &c->d_dpa, &c->d_ones};
+    for (void** p : ptrs) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+  }
+  return rc;
 }
 
 int require_device(const bbwadg_ctx* c) {
@@ -902,6 +964,109 @@ int bbwadg_project_fn(bbwadg_ctx* c, double (*fn)(double, double, double, void*)
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // src is a local buffer
   if (e != hipSuccess) return fail(BBWADG_EHIP, "state upload: %s", hipGetErrorString(e));
   return 0;
+}
+
+int bbwadg_dense_npoints(const bbwadg_ctx* c, int64_t* nq) {
+  if (!c || !nq) return fail(BBWADG_EINVAL, "NULL argument");
+  const int64_t n = dense_rule_n(c);
+  *nq = n * n * n;
+  return 0;
+}
+
+int bbwadg_dense_points(const bbwadg_ctx* ctx, int64_t k0, int64_t k1, double* xyz_out) {
+  if (!ctx || !xyz_out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (k0 < 0 || k1 > ctx->K || k0 > k1) return fail(BBWADG_EINVAL, "bad element range");
+  auto* c = const_cast<bbwadg_ctx*>(ctx);
+  const Projector& pr = get_dense(c);
+  for (int64_t k = k0; k < k1; ++k) {
+    const int32_t* v = &c->etov[4 * k];
+    for (int q = 0; q < pr.nq; ++q)
+      for (int d = 0; d < 3; ++d) {
+        ld x = 0;
+        for (int j = 0; j < 4; ++j) x += pr.lam[q][j] * (ld)c->xyz[3 * (size_t)v[j] + d];
+        xyz_out[((size_t)(k - k0) * pr.nq + q) * 3 + d] = (double)x;
+      }
+  }
+  return 0;
+}
+
+int bbwadg_dense_set_c2(bbwadg_ctx* c, const double* c2q, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (c->dtype != BBWADG_F64) return fail(BBWADG_EINVAL, "the dense WADG baseline runs in FP64 contexts only");
+  if (!c2q && !c->c2_set) return fail(BBWADG_EC2, "c^2 not set (pass point values or set c^2_M first)");
+  if ((rc = dense_tables(c))) return rc;
+  const Projector& pr = c->dense;
+  const int64_t K = c->K;
+  const int nq = pr.nq, nqp = c->dense_nqp, mp = c->Mp;
+  std::vector<double> buf((size_t)K * nqp, 0.0);
+  std::vector<ld> bm;
+  if (!c2q) {  // c^2_M at the dense points
+    auto AM = mi3_list(c->M);
+    bm.resize((size_t)nq * mp);
+    for (int q = 0; q < nq; ++q)
+      for (int b = 0; b < mp; ++b) bm[(size_t)q * mp + b] = bernstein(c->M, AM[b], pr.lam[q]);
+  }
+  std::atomic<int> bad{0};
+  parallel_for(0, K, [&](int64_t a, int64_t b) {
+    for (int64_t k = a; k < b; ++k)
+      for (int q = 0; q < nq; ++q) {
+        double v;
+        if (c2q) {
+          v = c2q[(size_t)k * nq + q];
+        } else {
+          ld acc = 0;
+          for (int j = 0; j < mp; ++j) acc += bm[(size_t)q * mp + j] * (ld)c->c2[(size_t)k * mp + j];
+          v = (double)acc;
+        }
+        if (!std::isfinite(v) || !(v > 0)) bad.store(1, std::memory_order_relaxed);
+        buf[(size_t)k * nqp + q] = v;
+      }
+  });
+  if (bad.load()) return fail(BBWADG_EC2, "c^2 at the dense points must be finite and positive");
+  if (!c->d_c2q && (rc = dmalloc(&c->d_c2q, buf.size() * 8))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(c->d_c2q, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // buf is a local buffer
+  if (e != hipSuccess) return fail(BBWADG_EHIP, "c^2 point values upload: %s", hipGetErrorString(e));
+  c->c2q_set = true;
+  return 0;
+}
+
+int bbwadg_dense_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!r || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (!c->c2q_set) return fail(BBWADG_EC2, "call bbwadg_dense_set_c2 first");
+  DenseArgs a{};
+  a.r = (const double*)r;
+  a.out = (double*)out;
+  a.va = (const double*)c->d_dva;
+  a.pa = (const double*)c->d_dpa;
+  a.c2q = (const double*)c->d_c2q;
+  a.K = c->K;
+  a.nqp = c->dense_nqp;
+  a.nqc = c->dense_nqp / 16;
+  int e = launch_wadg_dense(c->N, a, stream);
+  if (e) return fail(BBWADG_EHIP, "dense update launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
+}
+
+int bbwadg_rhs_dense(bbwadg_ctx* c, const void* q, void* rhs, double t, void* stream) {
+  (void)t;
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !rhs) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (q == rhs) return fail(BBWADG_EINVAL, "q and rhs must not overlap");
+  if (!c->c2q_set) return fail(BBWADG_EC2, "call bbwadg_dense_set_c2 first");
+  hipStream_t s = (hipStream_t)stream;
+  StageArgs<double> a = make_args<double>(c);  // the plain DG right-hand side: c^2 = 1, M = 0
+  a.c2 = (const double*)c->d_ones;
+  a.qin = (const double*)q;
+  a.qout = (double*)rhs;
+  int e = launch_stage_f64(c->N, 0, false, a, s);
+  if (e) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
+  return bbwadg_dense_update(c, rhs, rhs, stream);  // the p field, in place
 }
 
 int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3) {

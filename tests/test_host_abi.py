@@ -173,3 +173,19 @@ def test_coef_index_matches_documented_order(bb):
     for N in (1, 4, 9, 13):
         for i, (a0, a1, a2, a3) in enumerate(multi_indices(N)):
             assert bb.coef_index(a1, a2, a3) == i
+
+
+def test_dense_rule_points_match_oracle_volume_rule(bb):
+    """The dense WADG rule is the oracle's volume rule (exact to degree 2N+M): same points."""
+    xyz, etov = kuhn_cube_mesh(1)
+    for N, M in [(2, 1), (5, 2), (9, 4)]:
+        s = bb.Solver(xyz, etov, N, M, host_only=True)
+        o = Oracle(xyz, etov, N, M)
+        n = (2 * N + M + 2) // 2
+        assert s.dense_npoints() == n ** 3 == len(o.wq)
+        X = s.dense_points()
+        Y = o.mesh.map_points(o.rq, o.sq, o.tq)
+        for k in range(s.K):
+            a = X[k][np.lexsort(X[k].T)]
+            b = Y[k][np.lexsort(Y[k].T)]
+            assert np.allclose(a, b, atol=1e-13)
