@@ -31,6 +31,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 
@@ -887,10 +888,15 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
   using L = StageLayout<real, N, M, EW>;
   constexpr int WPB = L::WPB;
   auto kern = stage_kernel<real, N, M, EW, WPB, UPDATE>;
-  static int grid = 0;  // persistent grid: resident blocks on the device, a multiple of 8
+  // persistent grid: the blocks resident on the current device, a multiple of 8; computed
+  // once per device (benign if two threads compute it concurrently: same value)
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> grids[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return (int)hipErrorInvalidDevice;
+  int grid = dev < kMaxDevices ? grids[dev].load(std::memory_order_relaxed) : 0;
   if (grid == 0) {
-    int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return (int)hipErrorInvalidDevice;
+    int ncu = 0;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (ncu <= 0) ncu = 256;
     int per_cu = 0;
@@ -906,6 +912,7 @@ int launch_stage_typed(const StageArgs<real>& a, void* stream) {
     if (per_cu <= 0) per_cu = 1;
     grid = ncu * per_cu;
     grid = (grid / 8) * 8 > 0 ? (grid / 8) * 8 : grid;
+    if (dev < kMaxDevices) grids[dev].store(grid, std::memory_order_relaxed);
   }
   const int64_t groups = (a.K + EW - 1) / EW;
   const int64_t need = (groups + L::TPB - 1) / L::TPB;  // one team per element group
