@@ -229,6 +229,47 @@ def wadg_compare(n_list, m_list, reps):
     return out
 
 
+def rates_sweep(n_list, m_list, meshes, T=0.5, cfl=0.5):
+    """The 3D manufactured solution of paper Section 6.1 (c^2 = 1 + sin sin sin / 2 projected
+    onto P^M, pressure source, p = 0 walls) to time T: L^2 errors of the pressure and of the
+    velocity on each Kuhn cube and the observed rates between consecutive meshes, in FP64."""
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from workloads import c2_sinusoid, kuhn_cube_mesh, manufactured_solution, manufactured_source
+
+    def fields(t):
+        return [lambda x, y, z, i=i: manufactured_solution(x, y, z, t)[i] for i in range(4)]
+
+    out = []
+    for n in n_list:
+        for m in m_list:
+            if m > n:
+                continue
+            errs = []
+            for cells in meshes:
+                xyz, etov = kuhn_cube_mesh(cells)
+                s = bb.Solver(xyz, etov, n, m, dtype="f64")
+                s.project_c2(c2_sinusoid)
+                s.set_source(manufactured_source(c2_sinusoid), omega=np.pi)
+                nsteps = int(np.ceil(T / s.suggest_dt(cfl)))
+                q = s.to_device(s.initial_state(fields(0.0)))
+                res = torch.zeros_like(q)
+                s.step(q, res, T / nsteps, nsteps)
+                torch.cuda.synchronize()
+                errs.append(s.l2error2(q, fields(T)))
+                del s, q, res
+            E = np.array(errs)
+            ep, eu = np.sqrt(E[:, 0]), np.sqrt(E[:, 1:].sum(1))
+            e = {"N": n, "M": m, "cells": list(meshes), "l2_error_p": ep.tolist(), "l2_error_u": eu.tolist(),
+                 "rates_p": np.log2(ep[:-1] / ep[1:]).tolist(), "rates_u": np.log2(eu[:-1] / eu[1:]).tolist(),
+                 "paper_rate_p": 2 if m == 0 else min(n + 1, m + 3)}
+            out.append(e)
+            print(json.dumps({"rates_progress": e}), file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+    return out
+
+
 def c2_bumps_medium():
     from workloads import c2_gaussian_bumps
     return c2_gaussian_bumps(0)
@@ -249,6 +290,8 @@ def main():
                     help="instead of the default workload: dense quadrature WADG vs the Bernstein update, N = 2..9")
     ap.add_argument("--c3", action="store_true",
                     help="instead of the default workload: N = 4..9, M = N/2 on the three-layer medium, FP64 and FP32")
+    ap.add_argument("--rates", action="store_true",
+                    help="instead of the default workload: manufactured-solution errors and rates, N = 1..6, M = 0..3")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -263,6 +306,11 @@ def main():
         res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
         print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
+        return
+    if args.rates:
+        res = rates_sweep(range(1, 7), range(0, 4), (2, 4, 8, 16))
+        print(json.dumps({"workload": "manufactured solution on the unit cube, T = 0.5, CFL 0.5", "unit": "L2 error",
+                          "dtype": "f64", "rates": res}), flush=True)
         return
     if args.c3:
         res = c3_sweep(args.steps, args.warmup)

@@ -148,18 +148,25 @@ int bbwadg_get_c2(const bbwadg_ctx* ctx, double* c2_coef);
  * Section 3.1), derivatives by the sparse Bernstein stencils (Section 4), the lift by
  * L^f = E_L L_0 (Section 4), the c^2 product by eq. (mcoeff) and Pi_N by the telescoped
  * projection eq. (telescope) (Section 5). q, rhs: device [4][K][Np] of dtype, must not
- * overlap. t is accepted for forcing terms and currently unused. */
+ * overlap. With a pressure source (bbwadg_set_source) r_p gains Pi_N f(., t). */
 int bbwadg_rhs(bbwadg_ctx* ctx, const void* q, void* rhs, double t, void* stream);
 
 /* Advance q in place by nsteps steps of the five-stage, 2N-storage fourth-order
  * Runge-Kutta scheme of Carpenter and Kennedy (paper Section 6.3.1): per stage
  * res = a_k res + dt rhs(q), q = q + b_k res. res: device [4][K][Np], the 2N-storage
  * register; zero it before the first step of a run. nsteps >= 0. q and res must not
- * overlap. Each stage is one fused kernel that reads the state from one buffer and
+ * overlap. Stage k of step n is taken at time t0 + (n + c_k) dt (for the source). Each stage is one fused kernel that reads the state from one buffer and
  * writes the next state to the other (q or the context's internal buffer); an odd
  * total stage count ends with one device copy back into q. */
 int bbwadg_step(bbwadg_ctx* ctx, void* q, void* res, double t0, double dt, int32_t nsteps,
                 void* stream);
+
+/* Pressure source for manufactured solutions (paper Section 6.1): the first equation becomes
+ * (1/c^2) p_t + div u = f with f(x, t) = amp sin(omega t + phase) g(x), and the WADG update
+ * applies to r_p + Pi_N f, i.e. dp/dt = Pi_N(c^2_M (r_p + Pi_N f)). g: host FP64 Bernstein
+ * coefficients [K][Np] of Pi_N g (e.g. from bbwadg_project_samples with degree N), copied;
+ * NULL removes the source. EINVAL for non-finite input. */
+int bbwadg_set_source(bbwadg_ctx* ctx, const double* g, double amp, double omega, double phase);
 
 /* dt = cfl / (c_max C_N max_{k,f} Fscale), C_N = (N+1)(N+3)/3, c_max^2 = the largest
  * c^2 Bernstein coefficient (an upper bound of c^2_M by the convex-hull property). */

@@ -91,6 +91,7 @@ class Oracle:
             self.Lf.append(self.Minv @ (Vf.T * wf[None, :]))
         self._build_neighbour_groups()
         self.c2q = None
+        self.src = None
 
     # ------------------------------------------------------------- neighbours
     def _build_neighbour_groups(self):
@@ -212,10 +213,28 @@ class Oracle:
                 nb[1:, bm] = own[1:, bm] - 2.0 * un[None] * n.T[:, :, None]
         return own, nb
 
-    def rhs(self, Q, pre_wadg: bool = False):
-        """Time derivative of the state Q [4, K, Np] (orthonormal coefficients).
+    def set_source(self, g_fn, amp: float = 1.0, omega: float = 0.0, phase: float = 0.0, nproj=None):
+        """Pressure source f(x, t) = amp sin(omega t + phase) g(x): the first equation becomes
+        (1/c^2) p_t + div u = f (the manufactured solutions of paper Section 6.1). Read as
+        dp/dt = Pi_N(c^2 (r_p + Pi_N f)) with Pi_N f the per-element L^2 projection. ``g_fn``
+        is a vectorised function or the orthonormal coefficients [K, Np] of Pi_N g."""
+        if callable(g_fn):
+            self.src = self.project_modal(g_fn, self.N, nproj)
+        else:
+            self.src = np.array(g_fn, dtype=np.float64).reshape(self.mesh.K, self.Np)
+        self.src_time = (float(amp), float(omega), float(phase))
 
-        With ``pre_wadg`` the p-component is r_p, before the weight-adjusted step."""
+    def source_factor(self, t: float) -> float:
+        if self.src is None:
+            return 0.0
+        amp, omega, phase = self.src_time
+        return amp * np.sin(omega * t + phase)
+
+    def rhs(self, Q, pre_wadg: bool = False, t: float = 0.0):
+        """Time derivative of the state Q [4, K, Np] (orthonormal coefficients) at time t.
+
+        With ``pre_wadg`` the p-component is r_p (with the source, if any), before the
+        weight-adjusted step."""
         Q = np.asarray(Q, dtype=np.float64)
         msh = self.mesh
         G = msh.G
@@ -239,6 +258,8 @@ class Oracle:
             lu = sc * (Fu @ self.Lf[f].T)
             for i in range(3):
                 ru[i] += n[:, i][:, None] * lu
+        if self.src is not None:
+            rp += self.source_factor(t) * self.src
         if pre_wadg:
             return np.concatenate([rp[None], ru])
         if self.c2q is None:
@@ -246,13 +267,14 @@ class Oracle:
         dp = (self.values_at_quad(rp) * self.c2q) @ self.Pq.T
         return np.concatenate([dp[None], ru])
 
-    def step(self, Q, res, dt: float, nsteps: int):
-        """Advance by nsteps low-storage RK4 steps; res is the 2N-storage register."""
+    def step(self, Q, res, dt: float, nsteps: int, t0: float = 0.0):
+        """Advance by nsteps low-storage RK4 steps from time t0; res is the 2N-storage
+        register. Stage k of step n is evaluated at t0 + (n + c_k) dt."""
         Q = np.array(Q, dtype=np.float64)
         res = np.array(res, dtype=np.float64)
-        for _ in range(nsteps):
-            for a, b in zip(LSRK4_A, LSRK4_B):
-                R = self.rhs(Q)
+        for n in range(nsteps):
+            for a, b, c in zip(LSRK4_A, LSRK4_B, LSRK4_C):
+                R = self.rhs(Q, t=t0 + (n + c) * dt)
                 res = a * res + dt * R
                 Q = Q + b * res
         return Q, res

@@ -29,7 +29,7 @@ EXPORTS = (
     "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
     "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
-    "bbwadg_rhs_dense",
+    "bbwadg_rhs_dense", "bbwadg_set_source",
     "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_dense_set_c2": (C.c_int, [vp, vp, vp]),
         "bbwadg_dense_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_rhs_dense": (C.c_int, [vp, vp, vp, dbl, vp]),
+        "bbwadg_set_source": (C.c_int, [vp, vp, dbl, dbl, dbl]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }
@@ -272,6 +273,19 @@ class Solver:
     def initial_state(self, fns) -> np.ndarray:
         """Host FP64 Bernstein coefficients [4, K, Np] of four functions (p, u, v, w)."""
         return np.stack([self.project_function(f, self.N) for f in fns])
+
+    def set_source(self, g=None, amp: float = 1.0, omega: float = 0.0, phase: float = 0.0):
+        """Pressure source f = amp sin(omega t + phase) g(x): g is a vectorised function (projected
+        onto P^N here) or Bernstein coefficients [K, Np]; None removes the source."""
+        if g is None:
+            _check(self._lib.bbwadg_set_source(self._ctx, None, 0.0, 0.0, 0.0))
+            return None
+        coef = self.project_function(g, self.N) if callable(g) else np.ascontiguousarray(g, dtype=np.float64)
+        if coef.shape != (self.K, self.Np):
+            raise ValueError(f"source coefficients must be [{self.K}, {self.Np}]")
+        _check(self._lib.bbwadg_set_source(self._ctx, C.c_void_p(coef.ctypes.data), float(amp), float(omega),
+                                           float(phase)))
+        return coef
 
     def suggest_dt(self, cfl: float) -> float:
         dt = C.c_double()

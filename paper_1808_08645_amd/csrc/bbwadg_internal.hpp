@@ -31,6 +31,8 @@ struct StageArgs {
   real tau_p, tau_u;
   int32_t bc;             // 0: p = 0 walls, 1: rigid walls
   real rk_a, rk_b, dt;    // stage coefficients (step mode)
+  const real* src;        // [K][Np] pressure source g (coefficients), or null
+  real src_amp;           // s(t) of the source f = s(t) g(x) at this stage's time
   real cj[kMaxN + 1];     // telescoped projection coefficients c_j
 };
 

@@ -285,6 +285,9 @@ struct bbwadg_ctx {
   void* d_c2q = nullptr;        // [K][dense_nqp] c^2 at the dense points
   void* d_ones = nullptr;       // [K] ones: c^2 = 1 for the plain DG right-hand side
   bool c2q_set = false;
+  // pressure source f(x, t) = amp sin(omega t + phase) g(x)
+  void* d_src = nullptr;        // [K][Np] coefficients of g (dtype)
+  double src_amp = 0, src_omega = 0, src_phase = 0;
 };
 
 namespace {
@@ -313,7 +316,8 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 void free_device(bbwadg_ctx* c) {
   void** ptrs[] = {&c->d_geo,     &c->d_conn,    &c->d_c2,         &c->d_c2k, &c->d_q2,
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
-                   &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones};
+                   &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
+                   &c->d_src};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -391,7 +395,14 @@ StageArgs<real> make_args(const bbwadg_ctx* c) {
   a.tau_u = (real)c->tau_u;
   a.bc = c->bc;
   for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  a.src = (const real*)c->d_src;
+  a.src_amp = real(0);
   return a;
+}
+
+// s(t) of the pressure source at time t (0 without a source).
+double source_factor(const bbwadg_ctx* c, double t) {
+  return c->d_src ? c->src_amp * std::sin(c->src_omega * t + c->src_phase) : 0.0;
 }
 
 const double kRkA[5] = {0.0,
@@ -399,6 +410,11 @@ const double kRkA[5] = {0.0,
                         -2404267990393.0 / 2016746695238.0,
                         -3550918686646.0 / 2091501179385.0,
                         -1275806237668.0 / 842570457699.0};
+const double kRkC[5] = {0.0,
+                        1432997174477.0 / 9575080441755.0,
+                        2526269341429.0 / 6820363183787.0,
+                        2006345519317.0 / 3224310063776.0,
+                        2802321613138.0 / 2924317926251.0};
 const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
                         5161836677717.0 / 13612068292357.0,
                         1720146321549.0 / 2090206949498.0,
@@ -406,10 +422,12 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
                         2277821191437.0 / 14882151754819.0};
 
 int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, double ra, double rb,
-           double dt, hipStream_t s) {
+           double dt, double t, hipStream_t s) {
   int e;
+  const double sf = source_factor(c, t);
   if (c->dtype == BBWADG_F64) {
     StageArgs<double> a = make_args<double>(c);
+    a.src_amp = sf;
     a.qin = (const double*)qin;
     a.qout = (double*)qout;
     a.res = (double*)res;
@@ -419,6 +437,7 @@ int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, d
     e = launch_stage_f64(c->N, c->M, update, a, s);
   } else {
     StageArgs<float> a = make_args<float>(c);
+    a.src_amp = (float)sf;
     a.qin = (const float*)qin;
     a.qout = (float*)qout;
     a.res = (float*)res;
@@ -845,30 +864,28 @@ int bbwadg_project_c2(bbwadg_ctx* c, double (*fn)(double, double, double, void*)
 }
 
 int bbwadg_rhs(bbwadg_ctx* c, const void* q, void* rhs, double t, void* stream) {
-  (void)t;
   int rc = require_device(c);
   if (rc) return rc;
   if (!q || !rhs) return fail(BBWADG_EINVAL, "NULL state pointer");
   if (q == rhs) return fail(BBWADG_EINVAL, "q and rhs must not overlap");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = sync_c2(c, s))) return rc;
-  return launch(c, false, q, rhs, nullptr, 0.0, 0.0, 0.0, s);
+  return launch(c, false, q, rhs, nullptr, 0.0, 0.0, 0.0, t, s);
 }
 
 int bbwadg_step(bbwadg_ctx* c, void* q, void* res, double t0, double dt, int32_t nsteps, void* stream) {
-  (void)t0;
   int rc = require_device(c);
   if (rc) return rc;
   if (!q || !res) return fail(BBWADG_EINVAL, "NULL state pointer");
   if (q == res) return fail(BBWADG_EINVAL, "q and res must not overlap");
-  if (nsteps < 0 || !std::isfinite(dt)) return fail(BBWADG_EINVAL, "bad nsteps or dt");
+  if (nsteps < 0 || !std::isfinite(dt) || !std::isfinite(t0)) return fail(BBWADG_EINVAL, "bad nsteps, dt or t0");
   hipStream_t s = (hipStream_t)stream;
   if ((rc = sync_c2(c, s))) return rc;
   void* cur = q;
   void* nxt = c->d_q2;
   for (int32_t n = 0; n < nsteps; ++n)
     for (int st = 0; st < 5; ++st) {
-      if ((rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, s))) return rc;
+      if ((rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, t0 + (n + kRkC[st]) * dt, s))) return rc;
       std::swap(cur, nxt);
     }
   if (cur != q) {
@@ -1053,7 +1070,6 @@ int bbwadg_dense_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
 }
 
 int bbwadg_rhs_dense(bbwadg_ctx* c, const void* q, void* rhs, double t, void* stream) {
-  (void)t;
   int rc = require_device(c);
   if (rc) return rc;
   if (!q || !rhs) return fail(BBWADG_EINVAL, "NULL state pointer");
@@ -1062,11 +1078,42 @@ int bbwadg_rhs_dense(bbwadg_ctx* c, const void* q, void* rhs, double t, void* st
   hipStream_t s = (hipStream_t)stream;
   StageArgs<double> a = make_args<double>(c);  // the plain DG right-hand side: c^2 = 1, M = 0
   a.c2 = (const double*)c->d_ones;
+  a.src_amp = source_factor(c, t);
   a.qin = (const double*)q;
   a.qout = (double*)rhs;
   int e = launch_stage_f64(c->N, 0, false, a, s);
   if (e) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
   return bbwadg_dense_update(c, rhs, rhs, stream);  // the p field, in place
+}
+
+int bbwadg_set_source(bbwadg_ctx* c, const double* g, double amp, double omega, double phase) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!g) {  // clear
+    if (c->d_src) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(c->d_src);
+      c->d_src = nullptr;
+    }
+    return 0;
+  }
+  if (!std::isfinite(amp) || !std::isfinite(omega) || !std::isfinite(phase))
+    return fail(BBWADG_EINVAL, "source time factor must be finite");
+  const size_t n = (size_t)c->K * c->Np;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(g[i])) return fail(BBWADG_EINVAL, "source coefficient %zu not finite", i);
+  if (!c->d_src && (rc = dmalloc(&c->d_src, n * c->rsz))) return rc;
+  if (c->dtype == BBWADG_F64) {
+    rc = upload(c->d_src, g, n * 8);
+  } else {
+    std::vector<float> f(g, g + n);
+    rc = upload(c->d_src, f.data(), n * 4);
+  }
+  if (rc) return rc;
+  c->src_amp = amp;
+  c->src_omega = omega;
+  c->src_phase = phase;
+  return 0;
 }
 
 int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3) {

@@ -696,13 +696,17 @@ void stage_kernel(const StageArgs<real> a) {
       }
       team_sync();
     }
-    // gather the four face lifts into every coefficient
+    // gather the four face lifts into every coefficient (and add the projected source to r_p)
     constexpr int BR = BA;  // r_p / alpha! (degree N); F and T are dead once level 0 is formed
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
       const int item = lane + TL * s;
       if (item < EW * NP) {
         const int e = item - (item / EW) * EW;
+        if (a.src) {  // the projected pressure source s(t) g (a uniform branch; no registers held otherwise)
+          const size_t idx = k0 + e < K ? (size_t)(k0 + e) * NP + item / EW : (size_t)k0 * NP;
+          acc[0][s] += a.src_amp * a.src[idx];
+        }
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const int lpf = lpo[s][f];

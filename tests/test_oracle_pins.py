@@ -315,3 +315,45 @@ def test_energy_nonincreasing_cube384_config():
         Q, res = o.step(Q, res, dt, 1)
         E.append(o.energy(Q))
     assert all(E[i + 1] <= E[i] * (1 + 1e-13) for i in range(10)), E
+
+
+# ------------------------------------------------------------------ manufactured source
+def test_source_enters_linearly_in_time():
+    """With Q = 0 the right-hand side is the source alone: dp/dt = s(t) Pi_N(c^2 Pi_N g),
+    du/dt = 0, with s(t) = amp sin(omega t + phase)."""
+    from workloads import c2_sinusoid, manufactured_source
+    xyz, etov = kuhn_cube_mesh(2)
+    o = Oracle(xyz, etov, 3, 1)
+    o.set_c2_function(c2_sinusoid, project=True)
+    o.set_source(manufactured_source(c2_sinusoid), amp=1.7, omega=2.0, phase=0.3)
+    Z = np.zeros((4, o.mesh.K, o.Np))
+    r1 = o.rhs(Z, t=0.1)
+    r2 = o.rhs(Z, t=0.6)
+    s1, s2 = 1.7 * np.sin(0.2 + 0.3), 1.7 * np.sin(1.2 + 0.3)
+    assert np.allclose(r1[0] * s2, r2[0] * s1, rtol=1e-12, atol=1e-14)
+    assert np.abs(r1[1:]).max() == 0.0
+    assert np.abs(r1[0]).max() > 0.1
+
+
+@pytest.mark.slow
+def test_manufactured_solution_rates():
+    """Paper Section 6.1 (observed rates): the pressure error against the manufactured solution
+    with c^2 = 1 + sin sin sin / 2 projected to P^M falls like h^r, r = min(N+1, M+3) (N=2,
+    M=1: r = 3) and r = 2 for M = 0 (N=2, M=0)."""
+    from workloads import c2_sinusoid, manufactured_solution, manufactured_source
+    T = 0.2
+    for M, want in ((1, 3.0), (0, 2.0)):
+        errs = []
+        for n in (2, 4):
+            xyz, etov = kuhn_cube_mesh(n)
+            o = Oracle(xyz, etov, 2, M)
+            o.set_c2_function(c2_sinusoid, project=True)
+            o.set_source(manufactured_source(c2_sinusoid), omega=np.pi)
+            fns = [lambda x, y, z, i=i: manufactured_solution(x, y, z, 0.0)[i] for i in range(4)]
+            Q = o.project_initial(fns)
+            nsteps = 8 * n
+            Q, _ = o.step(Q, np.zeros_like(Q), T / nsteps, nsteps)
+            ex = [lambda x, y, z, i=i: manufactured_solution(x, y, z, T)[i] for i in range(4)]
+            errs.append(np.sqrt(o.l2_error_sq(Q, ex)[0]))
+        rate = np.log2(errs[0] / errs[1])
+        assert rate > want - 0.6, (M, errs, rate)

@@ -31,6 +31,8 @@ __all__ = [
     "ic_gaussian_pulse",
     "exact_sin_mode",
     "exact_cos_mode",
+    "manufactured_solution",
+    "manufactured_source",
     "random_state",
     "random_c2_coefficients",
     "dim_p",
@@ -183,6 +185,24 @@ def exact_sin_mode(x, y, z, t):
     cx, cy, cz = np.cos(np.pi * x), np.cos(np.pi * y), np.cos(np.pi * z)
     s = np.sin(w * t) / np.sqrt(3.0)
     return (sx * sy * sz * np.cos(w * t), -cx * sy * sz * s, -sx * cy * sz * s, -sx * sy * cz * s)
+
+
+def manufactured_solution(x, y, z, t):
+    """The 3D manufactured solution of paper Section 6.1: returns (p, u, v, w) with
+    p = sin(pi x) sin(pi y) sin(pi z) cos(pi t) and u = -(cos sin sin, sin cos sin,
+    sin sin cos) sin(pi t); p = 0 on the walls of the unit cube."""
+    sx, sy, sz = np.sin(np.pi * x), np.sin(np.pi * y), np.sin(np.pi * z)
+    cx, cy, cz = np.cos(np.pi * x), np.cos(np.pi * y), np.cos(np.pi * z)
+    st = np.sin(np.pi * t)
+    return (sx * sy * sz * np.cos(np.pi * t), -cx * sy * sz * st, -sx * cy * sz * st, -sx * sy * cz * st)
+
+
+def manufactured_source(c2):
+    """Spatial part g of the source f = g(x) sin(pi t) that makes manufactured_solution solve
+    (1/c^2) p_t + div u = f, u_t + grad p = 0: g = (3 - 1/c^2) pi sin(pi x) sin(pi y) sin(pi z)."""
+    def g(x, y, z):
+        return (3.0 - 1.0 / c2(x, y, z)) * np.pi * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+    return g
 
 
 def exact_cos_mode(x, y, z, t):
