@@ -33,6 +33,7 @@ __all__ = [
     "exact_cos_mode",
     "manufactured_solution",
     "manufactured_source",
+    "receiver_grid",
     "random_state",
     "random_c2_coefficients",
     "dim_p",
@@ -203,6 +204,16 @@ def manufactured_source(c2):
     def g(x, y, z):
         return (3.0 - 1.0 / c2(x, y, z)) * np.pi * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
     return g
+
+
+def receiver_grid(n: int = 8, z: float = 1.0, shift=(0.5, 0.53125)):
+    """n x n receiver points ((i + sx)/n, (j + sy)/n, z) on a plane z = const, row-major in
+    (j, i). The default shift keeps them off the cell edges and face diagonals of the Kuhn
+    meshes with 8m cells per side, so each lies in the interior of one boundary face."""
+    i, j = np.meshgrid(np.arange(n), np.arange(n))
+    x = (i.ravel() + shift[0]) / n
+    y = (j.ravel() + shift[1]) / n
+    return np.stack([x, y, np.full(n * n, float(z))], axis=1)
 
 
 def exact_cos_mode(x, y, z, t):
