@@ -236,6 +236,46 @@ int bbwadg_dense_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream)
  * bbwadg_dense_update on the p field. q, rhs: device [4][K][Np] FP64, must not overlap. */
 int bbwadg_rhs_dense(bbwadg_ctx* ctx, const void* q, void* rhs, double t, void* stream);
 
+/* ---- receivers, misfit and its gradient with respect to c^2_M -------------------------
+ * Receivers sample the pressure after each step; the misfit of a run of nsteps steps is
+ * J = 1/2 sum_n sum_r (p(x_r, t_n) - d[n][r])^2. Its gradient with respect to the
+ * per-element Bernstein coefficients of c^2_M (the weight of the weight-adjusted projection,
+ * paper Section 3.1 and Section 5) is the exact discrete adjoint of the LSRK4 scheme. */
+
+/* Place nrec receivers at host FP64 points xyz [nrec][3]. Each lies in the lowest-numbered
+ * element whose barycentric coordinates are all >= -1e-10 (the pressure is discontinuous
+ * across elements, so a point on a shared face takes that element's value). The library keeps
+ * copies of the basis values there and of the row of (J_k M)^{-1}, M the Bernstein mass matrix.
+ * nrec = 0 removes them. EINVAL for a point outside the mesh or a non-finite coordinate. Works
+ * on host-only contexts (no device copies). */
+int bbwadg_set_receivers(bbwadg_ctx* ctx, int32_t nrec, const double* xyz);
+
+/* Host int32[nrec]: the element of each receiver. */
+int bbwadg_receiver_elements(const bbwadg_ctx* ctx, int32_t* elem_out);
+
+/* Run nsteps LSRK4 steps from the device state q0 [4][K][Np] (not modified; the source, if
+ * set, enters at the stage times t0 + (n + c_k) dt) and return the misfit in *misfit (host).
+ * data: device FP64 [nsteps][nrec] observed traces, or NULL for zeros. traces: device FP64
+ * [nsteps][nrec] for the computed traces, or NULL. grad: device FP64 [K][Mp] for dJ/dc (overwritten), or NULL
+ * to stop after the forward run.
+ *
+ * The backward pass takes the transposed stages in reverse order in the variables
+ * z = (M S)^{-1} lambda (S = diag(1, -1, -1, -1) reflects the velocity, M is the block mass
+ * matrix): the DG operator's symmetric part is the penalty alone, which does not couple p and
+ * u, so A^T (M S) = (M S) B W with B the plain DG operator and W the weight-adjusted
+ * projection, and each transposed stage is two stage-kernel launches. The forward states are
+ * checkpointed every checkpoint_every steps and each segment is recomputed once, storing the
+ * pressure part of B q for its 5 checkpoint_every stages. Device memory allocated and freed
+ * inside the call: about (5 + nsteps/checkpoint_every) states and, with grad,
+ * 5 checkpoint_every + 5 more; synchronises `stream`. EINVAL without receivers. */
+int bbwadg_misfit_gradient(bbwadg_ctx* ctx, const void* q0, double t0, double dt, int32_t nsteps, const double* data,
+                           int32_t checkpoint_every, double* traces, double* misfit, double* grad, void* stream);
+
+/* The transposed operator in the variables of bbwadg_misfit_gradient: out = B(W z), i.e.
+ * A^T (M S z) = M S out. For device states z, out [4][K][Np] of the context dtype (no
+ * overlap). Allocates two state-sized temporaries; synchronises `stream`. */
+int bbwadg_adjoint_apply(bbwadg_ctx* ctx, const void* z, void* out, void* stream);
+
 /* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
  * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
  * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .basis import bernstein_tet, dubiner_tet
+from .basis import bernstein_tet
 from .wadg import LSRK4_A, LSRK4_B, LSRK4_C, Oracle
 
 
@@ -48,11 +48,17 @@ def locate(mesh, pts, tol: float = 1e-10):
 
 
 class Receivers:
-    """Pressure samples at fixed points: p(x_r) = sum_j Q_p[k_r, j] phi_j(r_r)."""
+    """Pressure samples at fixed points: p(x_r) = sum_j Q_p[k_r, j] phi_j(r_r).
+
+    The modal values phi are taken through the Bernstein basis, which is regular at every
+    point of the element (the collapsed-coordinate form of the modal basis is singular at
+    one vertex): phi(r) = B(r) T^{-1}, with T the exact Bernstein-to-modal change of basis."""
 
     def __init__(self, o: Oracle, pts):
         self.elem, self.rst = locate(o.mesh, pts)
-        self.phi = dubiner_tet(o.N, self.rst[:, 0], self.rst[:, 1], self.rst[:, 2])  # [nrec, Np]
+        T = o.Pq @ bernstein_tet(o.N, o.rq, o.sq, o.tq)
+        Bx = bernstein_tet(o.N, self.rst[:, 0], self.rst[:, 1], self.rst[:, 2])  # [nrec, Np]
+        self.phi = Bx @ np.linalg.inv(T)
 
     def sample(self, Q):
         return np.einsum("rj,rj->r", Q[0, self.elem], self.phi)

@@ -29,7 +29,8 @@ EXPORTS = (
     "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
     "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
-    "bbwadg_rhs_dense", "bbwadg_set_source",
+    "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
+    "bbwadg_misfit_gradient", "bbwadg_adjoint_apply",
     "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
@@ -98,6 +99,10 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_dense_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_rhs_dense": (C.c_int, [vp, vp, vp, dbl, vp]),
         "bbwadg_set_source": (C.c_int, [vp, vp, dbl, dbl, dbl]),
+        "bbwadg_set_receivers": (C.c_int, [vp, i32, pd]),
+        "bbwadg_receiver_elements": (C.c_int, [vp, C.POINTER(C.c_int32)]),
+        "bbwadg_misfit_gradient": (C.c_int, [vp, vp, dbl, dbl, i32, vp, i32, vp, pd, vp, vp]),
+        "bbwadg_adjoint_apply": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }
@@ -286,6 +291,50 @@ class Solver:
         _check(self._lib.bbwadg_set_source(self._ctx, C.c_void_p(coef.ctypes.data), float(amp), float(omega),
                                            float(phase)))
         return coef
+
+    # ------------------------------------------------------------ receivers, misfit, gradient
+    def set_receivers(self, pts):
+        """Receivers at physical points [nrec, 3] (pressure sampled after every step)."""
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+        _check(self._lib.bbwadg_set_receivers(self._ctx, len(pts), _dptr(pts)))
+        self.nrec = len(pts)
+
+    def receiver_elements(self) -> np.ndarray:
+        out = np.empty(getattr(self, "nrec", 0), dtype=np.int32)
+        _check(self._lib.bbwadg_receiver_elements(self._ctx, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def misfit_gradient(self, q0, dt: float, nsteps: int, data=None, checkpoint_every: int = 50, t0: float = 0.0,
+                        gradient: bool = True):
+        """Misfit J = 1/2 sum (p(x_r, t_n) - data[n, r])^2 of nsteps LSRK4 steps from q0, the
+        traces [nsteps, nrec] (device FP64) and, with ``gradient``, dJ/dc [K, Mp] (device FP64)."""
+        import torch
+        self._check_state(q0, "q0")
+        nrec = getattr(self, "nrec", 0)
+        traces = torch.empty((nsteps, nrec), dtype=torch.float64, device="cuda")
+        dptr = None
+        if data is not None:
+            data = torch.as_tensor(data, dtype=torch.float64, device="cuda").contiguous()
+            if tuple(data.shape) != (nsteps, nrec):
+                raise ValueError(f"data must be [{nsteps}, {nrec}]")
+            dptr = C.c_void_p(data.data_ptr())
+        grad = torch.empty((self.K, self.Mp), dtype=torch.float64, device="cuda") if gradient else None
+        J = C.c_double()
+        _check(self._lib.bbwadg_misfit_gradient(self._ctx, C.c_void_p(q0.data_ptr()), float(t0), float(dt), int(nsteps),
+                                                dptr, int(checkpoint_every), C.c_void_p(traces.data_ptr()),
+                                                C.byref(J), C.c_void_p(grad.data_ptr()) if gradient else None,
+                                                self._stream()))
+        return J.value, grad, traces
+
+    def adjoint_apply(self, z, out=None):
+        """out = B(W z): the transposed operator in the mass-weighted, velocity-reflected variables."""
+        self._check_state(z, "z")
+        if out is None:
+            out = self.empty_state()
+        self._check_state(out, "out")
+        _check(self._lib.bbwadg_adjoint_apply(self._ctx, C.c_void_p(z.data_ptr()), C.c_void_p(out.data_ptr()),
+                                              self._stream()))
+        return out
 
     def suggest_dt(self, cfl: float) -> float:
         dt = C.c_double()

@@ -77,6 +77,30 @@ struct DenseArgs {
   int32_t nqp;        // NQP
 };
 int launch_wadg_dense(int N, const DenseArgs& a, void* stream);
+
+// Adjoint helpers (adjoint_kernel.hip); each returns a hipError_t value cast to int.
+template <typename real>
+struct C2GradArgs {
+  const real* y;       // [K][Np] pressure part of the DG right-hand side of the stage input
+  const real* v;       // [K][Np] pressure part of the reversed stage's adjoint variable
+  const double* vt;    // [Np][nq] Bernstein basis of degree N at the rule points
+  const double* bw;    // [nq][Mp] rule weight times the degree-M Bernstein basis
+  const double* J;     // [K]
+  double* grad;        // [K][Mp] accumulated
+  double scale;
+  int64_t K;
+  int32_t Np, Mp, nq;
+};
+template <typename real>
+int launch_lincomb(real* x, const real* y, double alpha, double beta, int64_t n, void* stream);
+template <typename real>
+int launch_sample(const real* qp, const int32_t* elem, const double* basis, int32_t nrec, int32_t Np, double* out,
+                  void* stream);
+template <typename real>
+int launch_inject(real* zp, const int32_t* elem, const double* kvec, const double* resid, int32_t nrec, int32_t Np,
+                  void* stream);
+template <typename real>
+int launch_c2grad(const C2GradArgs<real>& a, void* stream);
 int launch_quad_reduce(int dtype, int mode, const QuadReduceArgs& a, int nblocks, void* stream);
 
 }  // namespace bbw

@@ -288,6 +288,18 @@ struct bbwadg_ctx {
   // pressure source f(x, t) = amp sin(omega t + phase) g(x)
   void* d_src = nullptr;        // [K][Np] coefficients of g (dtype)
   double src_amp = 0, src_omega = 0, src_phase = 0;
+  // receivers (pressure samples) and the misfit gradient
+  int32_t nrec = 0;
+  std::vector<int32_t> rec_elem;      // [nrec] containing element
+  std::vector<double> rec_basis;      // [nrec][Np] B^N_alpha at the receiver
+  std::vector<double> rec_kvec;       // [nrec][Np] (J_k M)^{-1} of that row
+  void* d_rec_elem = nullptr;
+  void* d_rec_basis = nullptr;
+  void* d_rec_kvec = nullptr;
+  int adj_nq = 0;
+  void* d_adj_vt = nullptr;     // [Np][nq] B^N at a rule exact to degree 2N+M
+  void* d_adj_bw = nullptr;     // [nq][Mp] weight times B^M there
+  void* d_adj_ones = nullptr;   // [K] ones (dtype): c^2 = 1 for the plain DG operator
 };
 
 namespace {
@@ -317,7 +329,8 @@ void free_device(bbwadg_ctx* c) {
   void** ptrs[] = {&c->d_geo,     &c->d_conn,    &c->d_c2,         &c->d_c2k, &c->d_q2,
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
                    &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
-                   &c->d_src};
+                   &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_vt,
+                   &c->d_adj_bw,  &c->d_adj_ones};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -1121,6 +1134,344 @@ int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3) {
   const int s = a1 + a2 + a3;
   if (s > kMaxDeg) return fail(BBWADG_EINVAL, "degree %d above %d", s, kMaxDeg);
   return dimp(s - 1) + a3 * (2 * s + 3 - a3) / 2 + a2;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ receivers and the adjoint
+namespace {
+
+// b <- A^{-1} b for the symmetric positive definite A [n][n] (long-double Cholesky).
+void spd_solve(std::vector<ld> A, int n, std::vector<ld>& b) {
+  for (int j = 0; j < n; ++j) {
+    ld s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    const ld d = std::sqrt(s);
+    A[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      ld t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = t / d;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    ld t = b[i];
+    for (int k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * b[k];
+    b[i] = t / A[(size_t)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    ld t = b[i];
+    for (int k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * b[k];
+    b[i] = t / A[(size_t)i * n + i];
+  }
+}
+
+inline int launch_typed(int N, int M, bool update, const StageArgs<double>& a, hipStream_t s) {
+  return launch_stage_f64(N, M, update, a, s);
+}
+inline int launch_typed(int N, int M, bool update, const StageArgs<float>& a, hipStream_t s) {
+  return launch_stage_f32(N, M, update, a, s);
+}
+
+// One stage-kernel launch with the weight, source and degree M chosen by the caller: the
+// plain DG operator is M = 0 with c^2 = 1; the weight adjustment alone is a zero state with
+// the input passed as the source (amplitude 1), since the kernel adds the source to r_p
+// before the weight-adjusted projection.
+template <typename real>
+int stage_custom(bbwadg_ctx* c, int M, const void* c2, const void* src, double amp, bool update, const void* qin,
+                 void* qout, void* res, double ra, double rb, double dt, hipStream_t s) {
+  StageArgs<real> a = make_args<real>(c);
+  a.c2 = (const real*)c2;
+  a.src = (const real*)src;
+  a.src_amp = (real)amp;
+  a.qin = (const real*)qin;
+  a.qout = (real*)qout;
+  a.res = (real*)res;
+  a.rk_a = (real)ra;
+  a.rk_b = (real)rb;
+  a.dt = (real)dt;
+  const int e = launch_typed(c->N, M, update, a, s);
+  if (e) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  return e == hipSuccess ? 0 : fail(BBWADG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device buffers of one call, freed together (after the caller's stream has drained).
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    if (!ptrs.empty()) (void)hipDeviceSynchronize();  // also on error paths, with work in flight
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  int get(void** p, size_t bytes) {
+    int rc = dmalloc(p, bytes ? bytes : 8);
+    if (!rc) ptrs.push_back(*p);
+    return rc;
+  }
+};
+
+// The plain-DG weight (ones) and the gradient's rule tables, built on first use.
+int adjoint_setup(bbwadg_ctx* c) {
+  int rc;
+  if (!c->d_adj_ones) {
+    if (c->dtype == BBWADG_F64) {
+      std::vector<double> ones((size_t)c->K, 1.0);
+      if ((rc = dmalloc(&c->d_adj_ones, ones.size() * 8)) || (rc = upload(c->d_adj_ones, ones.data(), ones.size() * 8)))
+        return rc;
+    } else {
+      std::vector<float> ones((size_t)c->K, 1.0f);
+      if ((rc = dmalloc(&c->d_adj_ones, ones.size() * 4)) || (rc = upload(c->d_adj_ones, ones.data(), ones.size() * 4)))
+        return rc;
+    }
+  }
+  if (!c->d_adj_vt) {
+    const int n = (2 * c->N + c->M + 2) / 2;  // n points per direction: exact to degree 2n - 1 >= 2N + M
+    Projector pn, pm;
+    build_projector_rule(c->N, n, pn);
+    build_projector_rule(c->M, n, pm);
+    const int nq = pn.nq, Np = c->Np, Mp = c->Mp;
+    std::vector<double> vt((size_t)Np * nq), bw((size_t)nq * Mp);
+    for (int q = 0; q < nq; ++q) {
+      for (int i = 0; i < Np; ++i) vt[(size_t)i * nq + q] = pn.B[(size_t)q * Np + i];
+      for (int g = 0; g < Mp; ++g) bw[(size_t)q * Mp + g] = pm.w[q] * pm.B[(size_t)q * Mp + g];
+    }
+    if ((rc = dmalloc(&c->d_adj_vt, vt.size() * 8)) || (rc = upload(c->d_adj_vt, vt.data(), vt.size() * 8)) ||
+        (rc = dmalloc(&c->d_adj_bw, bw.size() * 8)) || (rc = upload(c->d_adj_bw, bw.data(), bw.size() * 8)))
+      return rc;
+    c->adj_nq = nq;
+  }
+  return 0;
+}
+
+template <typename real>
+int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, int32_t nsteps, const double* data,
+                          int32_t ckpt, double* traces, double* misfit, double* grad, hipStream_t s) {
+  int rc;
+  const int64_t K = c->K;
+  const int Np = c->Np, nrec = c->nrec;
+  const size_t n1 = (size_t)K * Np, n4 = 4 * n1, rb = sizeof(real);
+  const int C = std::min(ckpt, nsteps), nseg = (nsteps + C - 1) / C;
+  Scratch ws;
+  void *qa, *qb, *res, *ck, *tr = traces, *resid;
+  if ((rc = ws.get(&qa, n4 * rb)) || (rc = ws.get(&qb, n4 * rb)) || (rc = ws.get(&res, n4 * rb)) ||
+      (rc = ws.get(&ck, (size_t)nseg * n4 * rb)) || (rc = ws.get(&resid, (size_t)nsteps * nrec * 8)))
+    return rc;
+  if (!tr && (rc = ws.get(&tr, (size_t)nsteps * nrec * 8))) return rc;
+  if ((rc = hip_check(hipMemsetAsync(res, 0, n4 * rb, s), "memset")) ||
+      (rc = hip_check(hipMemcpyAsync(qa, q0, n4 * rb, hipMemcpyDeviceToDevice, s), "copy q0")))
+    return rc;
+  const int32_t* elem = (const int32_t*)c->d_rec_elem;
+  const double* rbasis = (const double*)c->d_rec_basis;
+  // forward: checkpoints at the start of every segment, receivers after every step
+  void* cur = qa;
+  void* nxt = qb;
+  for (int32_t n = 0; n < nsteps; ++n) {
+    if (n % C == 0 &&
+        (rc = hip_check(hipMemcpyAsync((char*)ck + (size_t)(n / C) * n4 * rb, cur, n4 * rb, hipMemcpyDeviceToDevice, s),
+                        "checkpoint")))
+      return rc;
+    for (int st = 0; st < 5; ++st) {
+      if ((rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, t0 + (n + kRkC[st]) * dt, s))) return rc;
+      std::swap(cur, nxt);
+    }
+    int e = launch_sample<real>((const real*)cur, elem, rbasis, nrec, Np, (double*)tr + (size_t)n * nrec, s);
+    if (e) return fail(BBWADG_EHIP, "receiver sample: %s", hipGetErrorString((hipError_t)e));
+  }
+  // misfit and residuals on the host (FP64)
+  const size_t nt = (size_t)nsteps * nrec;
+  std::vector<double> htr(nt), hd(nt, 0.0);
+  if ((rc = hip_check(hipMemcpyAsync(htr.data(), tr, nt * 8, hipMemcpyDeviceToHost, s), "traces download")))
+    return rc;
+  if (data && (rc = hip_check(hipMemcpyAsync(hd.data(), data, nt * 8, hipMemcpyDeviceToHost, s), "data download")))
+    return rc;
+  if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
+  double J = 0.0;
+  for (size_t i = 0; i < nt; ++i) {
+    if (!std::isfinite(hd[i])) return fail(BBWADG_EINVAL, "data value %zu not finite", i);
+    hd[i] = htr[i] - hd[i];
+    J += 0.5 * hd[i] * hd[i];
+  }
+  *misfit = J;
+  if (!grad) return hip_check(hipStreamSynchronize(s), "sync");
+  if ((rc = hip_check(hipMemcpyAsync(resid, hd.data(), nt * 8, hipMemcpyHostToDevice, s), "residual upload")) ||
+      (rc = adjoint_setup(c)))
+    return rc;
+  // backward in the variables z = (M S)^{-1} lambda: per reversed stage
+  //   v = z_r + b_k z_q;  grad += dt dW/dc(y_k, v);  z_q += dt B W v;  z_r = a_k v
+  void *ys, *zq, *v, *w4, *t4, *zero4;
+  if ((rc = ws.get(&ys, (size_t)C * 5 * n1 * rb)) || (rc = ws.get(&zq, n4 * rb)) || (rc = ws.get(&v, n4 * rb)) ||
+      (rc = ws.get(&w4, n4 * rb)) || (rc = ws.get(&t4, n4 * rb)) || (rc = ws.get(&zero4, n4 * rb)))
+    return rc;
+  if ((rc = hip_check(hipMemsetAsync(zq, 0, n4 * rb, s), "memset")) ||
+      (rc = hip_check(hipMemsetAsync(v, 0, n4 * rb, s), "memset")) ||
+      (rc = hip_check(hipMemsetAsync(zero4, 0, n4 * rb, s), "memset")) ||
+      (rc = hip_check(hipMemsetAsync(grad, 0, (size_t)K * c->Mp * 8, s), "memset")))
+    return rc;
+  C2GradArgs<real> ga{};
+  ga.vt = (const double*)c->d_adj_vt;
+  ga.bw = (const double*)c->d_adj_bw;
+  ga.J = (const double*)c->d_J;
+  ga.grad = grad;
+  ga.scale = dt;
+  ga.K = K;
+  ga.Np = Np;
+  ga.Mp = c->Mp;
+  ga.nq = c->adj_nq;
+  ga.v = (const real*)v;
+  const void* ones = c->d_adj_ones;
+  int e;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int32_t na = seg * C, nb = std::min(nsteps, na + C);
+    // recompute the segment, keeping y = (B q)_p of every stage input (source included)
+    if ((rc = hip_check(hipMemcpyAsync(qa, (char*)ck + (size_t)seg * n4 * rb, n4 * rb, hipMemcpyDeviceToDevice, s),
+                        "restore")))
+      return rc;
+    cur = qa;
+    nxt = qb;
+    for (int32_t n = na; n < nb; ++n)
+      for (int st = 0; st < 5; ++st) {
+        const double ts = t0 + (n + kRkC[st]) * dt;
+        void* yslot = (char*)ys + ((size_t)(n - na) * 5 + st) * n1 * rb;
+        if ((rc = stage_custom<real>(c, 0, ones, c->d_src, source_factor(c, ts), false, cur, t4, nullptr, 0, 0, 0, s)) ||
+            (rc = hip_check(hipMemcpyAsync(yslot, t4, n1 * rb, hipMemcpyDeviceToDevice, s), "copy y")) ||
+            (rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, ts, s)))
+          return rc;
+        std::swap(cur, nxt);
+      }
+    for (int32_t n = nb - 1; n >= na; --n) {
+      // dJ/dq after step n, then v = z_r + b_5 z_q with z_r = a_1 v = 0
+      if ((e = launch_inject<real>((real*)zq, elem, (const double*)c->d_rec_kvec, (const double*)resid + (size_t)n * nrec,
+                                   nrec, Np, s)) ||
+          (e = launch_lincomb<real>((real*)v, (const real*)zq, 0.0, kRkB[4], (int64_t)n4, s)))
+        return fail(BBWADG_EHIP, "adjoint bookkeeping: %s", hipGetErrorString((hipError_t)e));
+      for (int st = 4; st >= 0; --st) {
+        ga.y = (const real*)((char*)ys + ((size_t)(n - na) * 5 + st) * n1 * rb);
+        if ((e = launch_c2grad<real>(ga, s))) return fail(BBWADG_EHIP, "c2 gradient: %s", hipGetErrorString((hipError_t)e));
+        // w4 = (W v_p, v_u), t4 = B w4
+        if ((rc = stage_custom<real>(c, c->M, c->d_c2k, v, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s)) ||
+            (rc = hip_check(hipMemcpyAsync((char*)w4 + n1 * rb, (char*)v + n1 * rb, 3 * n1 * rb, hipMemcpyDeviceToDevice, s),
+                            "copy u")) ||
+            (rc = stage_custom<real>(c, 0, ones, nullptr, 0.0, false, w4, t4, nullptr, 0, 0, 0, s)))
+          return rc;
+        if ((e = launch_lincomb<real>((real*)zq, (const real*)t4, 1.0, dt, (int64_t)n4, s)) ||
+            (st > 0 && (e = launch_lincomb<real>((real*)v, (const real*)zq, kRkA[st], kRkB[st - 1], (int64_t)n4, s))))
+          return fail(BBWADG_EHIP, "adjoint bookkeeping: %s", hipGetErrorString((hipError_t)e));
+      }
+    }
+  }
+  return hip_check(hipStreamSynchronize(s), "sync");
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbwadg_set_receivers(bbwadg_ctx* c, int32_t nrec, const double* xyz) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (nrec < 0 || (nrec > 0 && !xyz)) return fail(BBWADG_EINVAL, "bad receiver count or NULL coordinates");
+  if (nrec > (1 << 20)) return fail(BBWADG_EINVAL, "too many receivers");
+  const int Np = c->Np;
+  std::vector<int32_t> elem(nrec, -1);
+  std::vector<double> basis((size_t)nrec * Np), kvec((size_t)nrec * Np);
+  auto A = mi3_list(c->N);
+  std::vector<ld> Mm = bernstein_mass(c->N);
+  for (int32_t r = 0; r < nrec; ++r) {
+    const double* x = xyz + 3 * (size_t)r;
+    if (!std::isfinite(x[0]) || !std::isfinite(x[1]) || !std::isfinite(x[2]))
+      return fail(BBWADG_EINVAL, "receiver %d not finite", r);
+    std::array<ld, 4> lam{};
+    for (int64_t k = 0; k < c->K && elem[r] < 0; ++k) {  // the lowest-numbered containing element
+      const double* v0 = &c->xyz[3 * (size_t)c->etov[4 * k]];
+      ld l[4];
+      ld sum = 0;
+      for (int j = 0; j < 3; ++j) {
+        ld t = 0;
+        for (int i = 0; i < 3; ++i) t += (ld)c->G[9 * k + 3 * i + j] * ((ld)x[i] - v0[i]);
+        l[j + 1] = t / 2;  // (r_j + 1) / 2
+        sum += l[j + 1];
+      }
+      l[0] = 1 - sum;
+      if (l[0] >= -1e-10L && l[1] >= -1e-10L && l[2] >= -1e-10L && l[3] >= -1e-10L) {
+        elem[r] = (int32_t)k;
+        for (int j = 0; j < 4; ++j) lam[j] = l[j];
+      }
+    }
+    if (elem[r] < 0) return fail(BBWADG_EINVAL, "receiver %d (%g, %g, %g) is outside the mesh", r, x[0], x[1], x[2]);
+    std::vector<ld> b(Np);
+    for (int i = 0; i < Np; ++i) b[i] = bernstein(c->N, A[i], lam);
+    for (int i = 0; i < Np; ++i) basis[(size_t)r * Np + i] = (double)b[i];
+    spd_solve(Mm, Np, b);
+    for (int i = 0; i < Np; ++i) kvec[(size_t)r * Np + i] = (double)(b[i] / c->J[elem[r]]);
+  }
+  c->rec_elem = elem;
+  c->rec_basis = basis;
+  c->rec_kvec = kvec;
+  c->nrec = nrec;
+  if (c->mode != BBWADG_DEVICE || nrec == 0) return 0;
+  int rc;
+  for (void** p : {&c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec})
+    if (*p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  if ((rc = dmalloc(&c->d_rec_elem, (size_t)nrec * 4)) || (rc = upload(c->d_rec_elem, elem.data(), (size_t)nrec * 4)) ||
+      (rc = dmalloc(&c->d_rec_basis, basis.size() * 8)) || (rc = upload(c->d_rec_basis, basis.data(), basis.size() * 8)) ||
+      (rc = dmalloc(&c->d_rec_kvec, kvec.size() * 8)) || (rc = upload(c->d_rec_kvec, kvec.data(), kvec.size() * 8)))
+    return rc;
+  return 0;
+}
+
+int bbwadg_receiver_elements(const bbwadg_ctx* c, int32_t* elem_out) {
+  if (!c || !elem_out) return fail(BBWADG_EINVAL, "NULL argument");
+  std::copy(c->rec_elem.begin(), c->rec_elem.end(), elem_out);
+  return 0;
+}
+
+int bbwadg_misfit_gradient(bbwadg_ctx* c, const void* q0, double t0, double dt, int32_t nsteps, const double* data,
+                           int32_t checkpoint_every, double* traces, double* misfit, double* grad, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q0 || !misfit) return fail(BBWADG_EINVAL, "NULL q0 or misfit");
+  if (c->nrec <= 0) return fail(BBWADG_EINVAL, "no receivers (call bbwadg_set_receivers)");
+  if (nsteps < 1 || checkpoint_every < 1 || !std::isfinite(dt) || !std::isfinite(t0))
+    return fail(BBWADG_EINVAL, "bad nsteps, checkpoint interval, dt or t0");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s))) return rc;
+  if (c->dtype == BBWADG_F64)
+    return misfit_gradient_typed<double>(c, q0, t0, dt, nsteps, data, checkpoint_every, traces, misfit, grad, s);
+  return misfit_gradient_typed<float>(c, q0, t0, dt, nsteps, data, checkpoint_every, traces, misfit, grad, s);
+}
+
+int bbwadg_adjoint_apply(bbwadg_ctx* c, const void* z, void* out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!z || !out) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (z == out) return fail(BBWADG_EINVAL, "z and out must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s)) || (rc = adjoint_setup(c))) return rc;
+  const size_t n1 = (size_t)c->K * c->Np, n4 = 4 * n1, rb = c->rsz;
+  Scratch ws;
+  void *zero4, *w4;
+  if ((rc = ws.get(&zero4, n4 * rb)) || (rc = ws.get(&w4, n4 * rb)) ||
+      (rc = hip_check(hipMemsetAsync(zero4, 0, n4 * rb, s), "memset")))
+    return rc;
+  // w4 = (W z_p, z_u): the weight-adjustment launch writes all four fields (u = 0), so the
+  // velocity is copied in after it
+  rc = c->dtype == BBWADG_F64 ? stage_custom<double>(c, c->M, c->d_c2k, z, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s)
+                              : stage_custom<float>(c, c->M, c->d_c2k, z, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s);
+  if (rc ||
+      (rc = hip_check(hipMemcpyAsync((char*)w4 + n1 * rb, (const char*)z + n1 * rb, 3 * n1 * rb, hipMemcpyDeviceToDevice, s),
+                      "copy u")))
+    return rc;
+  rc = c->dtype == BBWADG_F64
+           ? stage_custom<double>(c, 0, c->d_adj_ones, nullptr, 0.0, false, w4, out, nullptr, 0, 0, 0, s)
+           : stage_custom<float>(c, 0, c->d_adj_ones, nullptr, 0.0, false, w4, out, nullptr, 0, 0, 0, s);
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(s), "sync");  // the temporaries are freed on return
 }
 
 }  // extern "C"

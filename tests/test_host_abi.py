@@ -189,3 +189,22 @@ def test_dense_rule_points_match_oracle_volume_rule(bb):
             a = X[k][np.lexsort(X[k].T)]
             b = Y[k][np.lexsort(Y[k].T)]
             assert np.allclose(a, b, atol=1e-13)
+
+
+def test_receiver_location_matches_oracle(bb):
+    """The library and the oracle place receivers in the same elements (lowest-numbered
+    containing element), including points on shared faces and on the boundary."""
+    from oracle.adjoint import locate
+    from workloads import receiver_grid
+    xyz, etov = kuhn_cube_mesh(4)
+    s = bb.Solver(xyz, etov, 3, 1, host_only=True)
+    pts = np.concatenate([receiver_grid(8, 1.0), receiver_grid(4, 0.5, shift=(0.0, 0.0)),
+                          np.random.default_rng(8).uniform(0, 1, (30, 3))])
+    s.set_receivers(pts)
+    o = Oracle(xyz, etov, 3, 1)
+    elem, _ = locate(o.mesh, pts)
+    assert np.array_equal(s.receiver_elements(), elem)
+    with pytest.raises(bb.BBWADGError):
+        s.set_receivers([[0.5, 0.5, 1.2]])
+    with pytest.raises(bb.BBWADGError):
+        s.set_receivers([[0.5, np.nan, 0.2]])

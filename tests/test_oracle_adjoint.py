@@ -87,3 +87,16 @@ def test_zero_residual_gives_zero_gradient():
     data = misfit(o, Q0, 0.02, 4, rec, np.zeros((4, 4)))[1]
     J, g, _ = misfit_gradient(o, c, Q0, 0.02, 4, rec, data)
     assert J == 0.0 and np.all(g == 0.0)
+
+
+def test_receivers_sample_polynomials_exactly_at_any_point():
+    """A projected polynomial of degree <= N is reproduced at the receivers, including mesh
+    vertices (where the modal basis in collapsed coordinates is singular) and face points."""
+    xyz, etov = kuhn_cube_mesh(2)
+    o = Oracle(xyz, etov, 3, 0)
+    f = lambda x, y, z: 1.0 + x - 2.0 * y * z + 0.5 * x ** 3  # noqa: E731
+    Q = o.project_initial([f, f, f, f])
+    pts = np.array([[0.5, 0.5, 0.5], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.5, 0.0, 1.0], [0.25, 0.5, 0.75],
+                    [0.3, 0.6, 1.0], [0.123, 0.456, 0.789]])
+    rec = Receivers(o, pts)
+    assert np.allclose(rec.sample(Q), f(pts[:, 0], pts[:, 1], pts[:, 2]), rtol=0, atol=1e-12)
