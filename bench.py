@@ -270,6 +270,80 @@ def rates_sweep(n_list, m_list, meshes, T=0.5, cfl=0.5):
     return out
 
 
+def adjoint_bench(nsteps=500, ckpt=50, n_fd=20):
+    """Misfit gradient on 24^3 x 6 = 82,944 tets, N=4, M=2, rigid walls, 64 receivers on the
+    top face, nsteps LSRK4 steps at CFL 0.5, checkpoints every ckpt steps. The observed traces
+    come from a seeded target medium (bumps, seed 5); the gradient is taken at the bump medium
+    (seed 0). Times the forward run alone and forward + gradient in FP64 and FP32, compares the
+    FP32 gradient with the FP64 one, and checks the FP64 gradient against central differences
+    of the misfit on n_fd seeded coefficients."""
+    import time
+
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from workloads import c2_gaussian_bumps, ic_gaussian_pulse, kuhn_cube_mesh, receiver_grid
+    xyz, etov = kuhn_cube_mesh(24)
+    pulse = lambda x, y, z: ic_gaussian_pulse(x, y, z, centre=(0.5, 0.5, 0.85), width=0.1)  # noqa: E731
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    out = {"elements": int(etov.shape[0]), "N": 4, "M": 2, "receivers": 64, "steps": nsteps,
+           "checkpoint_every": ckpt}
+    grads = {}
+    for dtype in ("f64", "f32"):
+        s = bb.Solver(xyz, etov, 4, 2, dtype=dtype, bc="rigid")
+        s.set_receivers(receiver_grid(8, 1.0))
+        q0 = s.initial_state([pulse, zero, zero, zero])
+        q = s.to_device(q0)
+        if dtype == "f64":
+            target = s.project_c2(c2_gaussian_bumps(5))
+            c = s.project_c2(c2_gaussian_bumps(0))
+            dt = s.suggest_dt(0.5)
+            s.set_c2(target)
+            _, _, data = s.misfit_gradient(q, dt, nsteps, None, gradient=False)
+            out["dt"] = dt
+        s.set_c2(c)
+        s.misfit_gradient(q, dt, 5, data[:5].contiguous(), ckpt)  # warm-up (tables, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, _, _ = s.misfit_gradient(q, dt, nsteps, data, ckpt, gradient=False)
+        t1 = time.perf_counter()
+        J2, g, _ = s.misfit_gradient(q, dt, nsteps, data, ckpt)
+        t2 = time.perf_counter()
+        grads[dtype] = g.cpu().numpy()
+        dofs = s.K * s.Np * 4
+        out[dtype] = {"misfit": J, "forward_s": t1 - t0, "forward_and_gradient_s": t2 - t1,
+                      "gradient_over_forward": (t2 - t1) / (t1 - t0),
+                      "forward_gdof_updates_per_s": dofs * nsteps / (t1 - t0) / 1e9}
+        print(json.dumps({"adjoint_progress": {dtype: out[dtype]}}), file=sys.stderr, flush=True)
+        if dtype == "f64":
+            s64, q64 = s, q
+        else:
+            del s, q
+    g64, g32 = grads["f64"], grads["f32"]
+    out["f32_vs_f64_gradient_rel_l2"] = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    if n_fd <= 0:
+        return out
+    rng = np.random.default_rng(11)
+    big = np.nonzero(np.abs(g64).max(1) > 1e-2 * np.abs(g64).max())[0]
+    rel = []
+    for k in rng.choice(big, n_fd, replace=False):
+        b = int(rng.integers(s64.Mp))
+        h = 1e-4 * max(1.0, abs(c[k, b]))
+        cp, cm = c.copy(), c.copy()
+        cp[k, b] += h
+        cm[k, b] -= h
+        s64.set_c2(cp)
+        jp = s64.misfit_gradient(q64, dt, nsteps, data, ckpt, gradient=False)[0]
+        s64.set_c2(cm)
+        jm = s64.misfit_gradient(q64, dt, nsteps, data, ckpt, gradient=False)[0]
+        fd = (jp - jm) / (2 * h)
+        rel.append(abs(fd - g64[k, b]) / np.abs(g64).max())
+    s64.set_c2(c)
+    out["fd_check"] = {"coefficients": n_fd, "max_abs_diff_over_max_grad": float(max(rel)),
+                       "median": float(np.median(rel)), "step": "1e-4 max(1, |c|)"}
+    return out
+
+
 def c2_bumps_medium():
     from workloads import c2_gaussian_bumps
     return c2_gaussian_bumps(0)
@@ -292,6 +366,10 @@ def main():
                     help="instead of the default workload: N = 4..9, M = N/2 on the three-layer medium, FP64 and FP32")
     ap.add_argument("--rates", action="store_true",
                     help="instead of the default workload: manufactured-solution errors and rates, N = 1..6, M = 0..3")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="instead of the default workload: misfit gradient on 82,944 tets, N=4, M=2, 500 steps")
+    ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--fd", type=int, default=20, help="finite-difference checks of the adjoint gradient")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this path has no multi-GPU mode "
@@ -306,6 +384,11 @@ def main():
         res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
         print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
+        return
+    if args.adjoint:
+        res = adjoint_bench(args.adjoint_steps, 50, args.fd)
+        print(json.dumps({"workload": f"adjoint: cube 24^3x6, N=4, M=2, 64 receivers, {args.adjoint_steps} steps",
+                          "data": "synthetic", "adjoint": res}), flush=True)
         return
     if args.rates:
         res = rates_sweep(range(1, 7), range(0, 4), (2, 4, 8, 16))

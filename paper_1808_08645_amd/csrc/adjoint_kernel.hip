@@ -5,11 +5,12 @@
 // operator satisfies A^T (M S) = (M S) (B W), so in the variables z = (M S)^{-1} lambda every
 // transposed stage is a plain-DG right-hand side B applied after the weight adjustment W.
 // What is left for this file is elementwise and small:
-//   * lincomb      x = alpha x + beta y (the 2N-storage bookkeeping of the reversed stages);
+//   * lincomb, back_update   the 2N-storage bookkeeping of the reversed stages;
 //   * sample       pressure at the receivers, p(x_r) = sum_a q_p[k_r][a] B_a(x_r), in FP64;
 //   * inject       z_p[k_r] += resid_r (J_k M)^{-1} b_r (dJ/dq mapped into z);
 //   * c2grad       grad[k][g] += scale J_k sum_q w_q B^M_g(x_q) y(x_q) v(x_q): the derivative
-//                  of v^T M^{-1} M_{c^2} y with respect to the Bernstein coefficients of c^2_M.
+//                  of v^T M^{-1} M_{c^2} y with respect to the Bernstein coefficients of c^2_M,
+//                  a dense contraction per element, on the FP64 matrix cores.
 #include "bbwadg_internal.hpp"
 
 namespace bbw {
@@ -19,6 +20,17 @@ template <typename real>
 __global__ __launch_bounds__(256) void lincomb_kernel(real* x, const real* y, real alpha, real beta, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = alpha * x[i] + beta * y[i];
+}
+
+// One reversed stage's bookkeeping in one pass: z_q += dt t, then (if v_coef) v = a v + b z_q.
+template <typename real>
+__global__ __launch_bounds__(256) void back_update_kernel(real* zq, real* v, const real* t, real dt, real a, real b,
+                                                          int v_coef, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const real z = zq[i] + dt * t[i];
+    zq[i] = z;
+    if (v_coef) v[i] = a * v[i] + b * z;
+  }
 }
 
 // One wavefront per receiver.
@@ -48,49 +60,78 @@ __global__ __launch_bounds__(256) void inject_kernel(real* zp, const int32_t* el
   }
 }
 
-// One workgroup of 256 threads per element; each thread owns rule points q = tid + 256 i.
-// vt[a][q] = B^N_a(x_q) and bw[q][g] = w_q B^M_g(x_q) (rule of degree >= 2N + M).
-constexpr int kGradThreads = 256;
+// grad[k][g] += scale J_k sum_q w_q B^M_g(x_q) y_k(x_q) v_k(x_q) on the FP64 matrix cores,
+// with the tiling of the dense WADG kernel: a wavefront takes 16 elements; per chunk of 16
+// rule points it forms Y = V_q R_y and V = V_q R_v (the two products share every A operand),
+// multiplies them pointwise, and accumulates G (16 x 16 elements) += BW^T[:, chunk] (Y.V),
+// where BW^T holds w_q B^M_g(x_q) in rows g < Mp. Lane l holds A[l%16][l/16], B[l/16][l%16]
+// and D[4i + l/16][l%16] as element i of its result.
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <typename real>
-__global__ __launch_bounds__(kGradThreads) void c2grad_kernel(C2GradArgs<real> a) {
-  __shared__ double ys[256], vs[256];  // Np <= 220
-  __shared__ double red[kGradThreads / 64][16];
-  const int64_t k = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < a.Np; i += kGradThreads) {
-    ys[i] = (double)a.y[(size_t)k * a.Np + i];
-    vs[i] = (double)a.v[(size_t)k * a.Np + i];
+template <int NP>
+constexpr int grad_waves() {
+  constexpr int NPP = (NP + 15) / 16 * 16;
+  constexpr int per_wave = (2 * NPP * 16 + 16 * 16) * 8;  // two coefficient tiles and the product
+  return 61440 / per_wave >= 4 ? 4 : (61440 / per_wave >= 1 ? 61440 / per_wave : 1);
+}
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename real, int NP, int kWaves = grad_waves<NP>()>
+__global__ __launch_bounds__(64 * kWaves) void c2grad_kernel(C2GradArgs<real> a) {
+  constexpr int NPP = (NP + 15) / 16 * 16, NK = NPP / 4;
+  __shared__ double ry[kWaves][NPP][16], rv[kWaves][NPP][16], pt[kWaves][16][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t k0 = ((int64_t)blockIdx.x * kWaves + wave) * 16;
+  if (k0 >= a.K) return;  // waves only synchronise among their own lanes
+  for (int idx = lane; idx < NPP * 16; idx += 64) {
+    const int i = idx >> 4, e = idx & 15;
+    const bool ok = i < NP && k0 + e < a.K;
+    ry[wave][i][e] = ok ? (double)a.y[(size_t)(k0 + e) * NP + i] : 0.0;
+    rv[wave][i][e] = ok ? (double)a.v[(size_t)(k0 + e) * NP + i] : 0.0;
   }
-  __syncthreads();
-  double part[16];
+  wsync();
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int qc = 0; qc < a.nqc; ++qc) {
+    const double* va = a.va + (size_t)qc * NK * 64 + lane;
+    d4 uy = {0.0, 0.0, 0.0, 0.0}, uv = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int g = 0; g < 16; ++g) part[g] = 0.0;
-  for (int q = tid; q < a.nq; q += kGradThreads) {
-    double yq = 0.0, vq = 0.0;
-    for (int i = 0; i < a.Np; ++i) {
-      const double b = a.vt[(size_t)i * a.nq + q];
-      yq += b * ys[i];
-      vq += b * vs[i];
+    for (int ks = 0; ks < NK; ++ks) {
+      const double A = va[ks * 64];
+      uy = __builtin_amdgcn_mfma_f64_16x16x4f64(A, ry[wave][4 * ks + kq][col], uy, 0, 0, 0);
+      uv = __builtin_amdgcn_mfma_f64_16x16x4f64(A, rv[wave][4 * ks + kq][col], uv, 0, 0, 0);
     }
-    const double pr = yq * vq;
 #pragma unroll
-    for (int g = 0; g < 16; ++g)
-      if (g < a.Mp) part[g] += a.bw[(size_t)q * a.Mp + g] * pr;
-  }
+    for (int i = 0; i < 4; ++i) pt[wave][4 * i + kq][col] = uy[i] * uv[i];
+    wsync();
+    const double* bw = a.bwa + (size_t)qc * 4 * 64 + lane;
 #pragma unroll
-  for (int g = 0; g < 16; ++g) {
-    double s = part[g];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) red[wave][g] = s;
+    for (int ks = 0; ks < 4; ++ks)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bw[ks * 64], pt[wave][4 * ks + kq][col], acc, 0, 0, 0);
+    wsync();  // the next chunk overwrites pt
   }
-  __syncthreads();
-  if (tid < a.Mp) {
-    double s = 0.0;
+  if (k0 + col < a.K) {
+    const double f = a.scale * a.J[k0 + col];
 #pragma unroll
-    for (int w = 0; w < kGradThreads / 64; ++w) s += red[w][tid];
-    a.grad[(size_t)k * a.Mp + tid] += a.scale * a.J[k] * s;
+    for (int i = 0; i < 4; ++i) {
+      const int g = 4 * i + kq;
+      if (g < a.Mp) a.grad[(size_t)(k0 + col) * a.Mp + g] += f * acc[i];
+    }
   }
+}
+
+template <typename real, int NP>
+int launch_grad_typed(const C2GradArgs<real>& a, void* stream) {
+  constexpr int kWaves = grad_waves<NP>();
+  const int64_t tiles = (a.K + 15) / 16;
+  const int64_t blocks = (tiles + kWaves - 1) / kWaves;
+  hipLaunchKernelGGL((c2grad_kernel<real, NP>), dim3((unsigned)blocks), dim3(64 * kWaves), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
 }
 
 unsigned grid_for(int64_t n) {
@@ -105,6 +146,15 @@ int launch_lincomb(real* x, const real* y, double alpha, double beta, int64_t n,
   if (n <= 0) return 0;
   hipLaunchKernelGGL(lincomb_kernel<real>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, x, y, (real)alpha,
                      (real)beta, n);
+  return (int)hipGetLastError();
+}
+
+template <typename real>
+int launch_back_update(real* zq, real* v, const real* t, double dt, double a, double b, bool update_v, int64_t n,
+                       void* stream) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(back_update_kernel<real>, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, zq, v, t, (real)dt,
+                     (real)a, (real)b, update_v ? 1 : 0, n);
   return (int)hipGetLastError();
 }
 
@@ -125,20 +175,32 @@ int launch_inject(real* zp, const int32_t* elem, const double* kvec, const doubl
 }
 
 template <typename real>
-int launch_c2grad(const C2GradArgs<real>& a, void* stream) {
+int launch_c2grad(int N, const C2GradArgs<real>& a, void* stream) {
   if (a.K <= 0) return 0;
-  if (a.Np > 256 || a.Mp > 16) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(c2grad_kernel<real>, dim3((unsigned)a.K), dim3(kGradThreads), 0, (hipStream_t)stream, a);
-  return (int)hipGetLastError();
+  if (a.Mp > 16) return (int)hipErrorInvalidValue;
+  switch (N) {
+    case 1: return launch_grad_typed<real, dimp(1)>(a, stream);
+    case 2: return launch_grad_typed<real, dimp(2)>(a, stream);
+    case 3: return launch_grad_typed<real, dimp(3)>(a, stream);
+    case 4: return launch_grad_typed<real, dimp(4)>(a, stream);
+    case 5: return launch_grad_typed<real, dimp(5)>(a, stream);
+    case 6: return launch_grad_typed<real, dimp(6)>(a, stream);
+    case 7: return launch_grad_typed<real, dimp(7)>(a, stream);
+    case 8: return launch_grad_typed<real, dimp(8)>(a, stream);
+    case 9: return launch_grad_typed<real, dimp(9)>(a, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 template int launch_lincomb<double>(double*, const double*, double, double, int64_t, void*);
 template int launch_lincomb<float>(float*, const float*, double, double, int64_t, void*);
+template int launch_back_update<double>(double*, double*, const double*, double, double, double, bool, int64_t, void*);
+template int launch_back_update<float>(float*, float*, const float*, double, double, double, bool, int64_t, void*);
 template int launch_sample<double>(const double*, const int32_t*, const double*, int32_t, int32_t, double*, void*);
 template int launch_sample<float>(const float*, const int32_t*, const double*, int32_t, int32_t, double*, void*);
 template int launch_inject<double>(double*, const int32_t*, const double*, const double*, int32_t, int32_t, void*);
 template int launch_inject<float>(float*, const int32_t*, const double*, const double*, int32_t, int32_t, void*);
-template int launch_c2grad<double>(const C2GradArgs<double>&, void*);
-template int launch_c2grad<float>(const C2GradArgs<float>&, void*);
+template int launch_c2grad<double>(int, const C2GradArgs<double>&, void*);
+template int launch_c2grad<float>(int, const C2GradArgs<float>&, void*);
 
 }  // namespace bbw

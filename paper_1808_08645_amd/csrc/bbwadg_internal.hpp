@@ -79,20 +79,26 @@ struct DenseArgs {
 int launch_wadg_dense(int N, const DenseArgs& a, void* stream);
 
 // Adjoint helpers (adjoint_kernel.hip); each returns a hipError_t value cast to int.
+// Tables at the dense rule (exact to degree 2N + M), in MFMA operand order as DenseArgs:
+// va = V_q (NQP/16 x NPP/4 x 64) and bwa[qc][ks][lane] = w_q B^M_g(x_q) for
+// g = lane%16, q = 16 qc + 4 ks + lane/16 (zero for g >= Mp or padding points).
 template <typename real>
 struct C2GradArgs {
   const real* y;       // [K][Np] pressure part of the DG right-hand side of the stage input
   const real* v;       // [K][Np] pressure part of the reversed stage's adjoint variable
-  const double* vt;    // [Np][nq] Bernstein basis of degree N at the rule points
-  const double* bw;    // [nq][Mp] rule weight times the degree-M Bernstein basis
+  const double* va;
+  const double* bwa;   // [NQP/16][4][64]
   const double* J;     // [K]
   double* grad;        // [K][Mp] accumulated
   double scale;
   int64_t K;
-  int32_t Np, Mp, nq;
+  int32_t Mp, nqc;
 };
 template <typename real>
 int launch_lincomb(real* x, const real* y, double alpha, double beta, int64_t n, void* stream);
+template <typename real>
+int launch_back_update(real* zq, real* v, const real* t, double dt, double a, double b, bool update_v, int64_t n,
+                       void* stream);
 template <typename real>
 int launch_sample(const real* qp, const int32_t* elem, const double* basis, int32_t nrec, int32_t Np, double* out,
                   void* stream);
@@ -100,7 +106,7 @@ template <typename real>
 int launch_inject(real* zp, const int32_t* elem, const double* kvec, const double* resid, int32_t nrec, int32_t Np,
                   void* stream);
 template <typename real>
-int launch_c2grad(const C2GradArgs<real>& a, void* stream);
+int launch_c2grad(int N, const C2GradArgs<real>& a, void* stream);
 int launch_quad_reduce(int dtype, int mode, const QuadReduceArgs& a, int nblocks, void* stream);
 
 }  // namespace bbw

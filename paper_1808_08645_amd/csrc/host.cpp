@@ -296,9 +296,7 @@ struct bbwadg_ctx {
   void* d_rec_elem = nullptr;
   void* d_rec_basis = nullptr;
   void* d_rec_kvec = nullptr;
-  int adj_nq = 0;
-  void* d_adj_vt = nullptr;     // [Np][nq] B^N at a rule exact to degree 2N+M
-  void* d_adj_bw = nullptr;     // [nq][Mp] weight times B^M there
+  void* d_adj_bwa = nullptr;    // rule weight times B^M at the dense points, MFMA operand order
   void* d_adj_ones = nullptr;   // [K] ones (dtype): c^2 = 1 for the plain DG operator
 };
 
@@ -329,8 +327,8 @@ void free_device(bbwadg_ctx* c) {
   void** ptrs[] = {&c->d_geo,     &c->d_conn,    &c->d_c2,         &c->d_c2k, &c->d_q2,
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
                    &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
-                   &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_vt,
-                   &c->d_adj_bw,  &c->d_adj_ones};
+                   &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_bwa,
+                   &c->d_adj_ones};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -1227,21 +1225,21 @@ int adjoint_setup(bbwadg_ctx* c) {
         return rc;
     }
   }
-  if (!c->d_adj_vt) {
-    const int n = (2 * c->N + c->M + 2) / 2;  // n points per direction: exact to degree 2n - 1 >= 2N + M
-    Projector pn, pm;
-    build_projector_rule(c->N, n, pn);
-    build_projector_rule(c->M, n, pm);
-    const int nq = pn.nq, Np = c->Np, Mp = c->Mp;
-    std::vector<double> vt((size_t)Np * nq), bw((size_t)nq * Mp);
-    for (int q = 0; q < nq; ++q) {
-      for (int i = 0; i < Np; ++i) vt[(size_t)i * nq + q] = pn.B[(size_t)q * Np + i];
-      for (int g = 0; g < Mp; ++g) bw[(size_t)q * Mp + g] = pm.w[q] * pm.B[(size_t)q * Mp + g];
-    }
-    if ((rc = dmalloc(&c->d_adj_vt, vt.size() * 8)) || (rc = upload(c->d_adj_vt, vt.data(), vt.size() * 8)) ||
-        (rc = dmalloc(&c->d_adj_bw, bw.size() * 8)) || (rc = upload(c->d_adj_bw, bw.data(), bw.size() * 8)))
+  if (!c->d_adj_bwa) {
+    // V_q of the dense rule (exact to degree 2N + M) is shared with the dense WADG baseline
+    if ((rc = dense_tables(c))) return rc;
+    Projector pm;
+    build_projector_rule(c->M, dense_rule_n(c), pm);
+    const int nq = pm.nq, Mp = c->Mp, nqc = c->dense_nqp / 16;
+    std::vector<double> bwa((size_t)nqc * 4 * 64, 0.0);
+    for (int qc = 0; qc < nqc; ++qc)
+      for (int ks = 0; ks < 4; ++ks)
+        for (int l = 0; l < 64; ++l) {
+          const int g = l % 16, q = 16 * qc + 4 * ks + l / 16;
+          if (g < Mp && q < nq) bwa[((size_t)qc * 4 + ks) * 64 + l] = pm.w[q] * pm.B[(size_t)q * Mp + g];
+        }
+    if ((rc = dmalloc(&c->d_adj_bwa, bwa.size() * 8)) || (rc = upload(c->d_adj_bwa, bwa.data(), bwa.size() * 8)))
       return rc;
-    c->adj_nq = nq;
   }
   return 0;
 }
@@ -1311,15 +1309,14 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
       (rc = hip_check(hipMemsetAsync(grad, 0, (size_t)K * c->Mp * 8, s), "memset")))
     return rc;
   C2GradArgs<real> ga{};
-  ga.vt = (const double*)c->d_adj_vt;
-  ga.bw = (const double*)c->d_adj_bw;
+  ga.va = (const double*)c->d_dva;
+  ga.bwa = (const double*)c->d_adj_bwa;
   ga.J = (const double*)c->d_J;
   ga.grad = grad;
   ga.scale = dt;
   ga.K = K;
-  ga.Np = Np;
   ga.Mp = c->Mp;
-  ga.nq = c->adj_nq;
+  ga.nqc = c->dense_nqp / 16;
   ga.v = (const real*)v;
   const void* ones = c->d_adj_ones;
   int e;
@@ -1349,15 +1346,16 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
         return fail(BBWADG_EHIP, "adjoint bookkeeping: %s", hipGetErrorString((hipError_t)e));
       for (int st = 4; st >= 0; --st) {
         ga.y = (const real*)((char*)ys + ((size_t)(n - na) * 5 + st) * n1 * rb);
-        if ((e = launch_c2grad<real>(ga, s))) return fail(BBWADG_EHIP, "c2 gradient: %s", hipGetErrorString((hipError_t)e));
+        if ((e = launch_c2grad<real>(c->N, ga, s))) return fail(BBWADG_EHIP, "c2 gradient: %s", hipGetErrorString((hipError_t)e));
         // w4 = (W v_p, v_u), t4 = B w4
         if ((rc = stage_custom<real>(c, c->M, c->d_c2k, v, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s)) ||
             (rc = hip_check(hipMemcpyAsync((char*)w4 + n1 * rb, (char*)v + n1 * rb, 3 * n1 * rb, hipMemcpyDeviceToDevice, s),
                             "copy u")) ||
             (rc = stage_custom<real>(c, 0, ones, nullptr, 0.0, false, w4, t4, nullptr, 0, 0, 0, s)))
           return rc;
-        if ((e = launch_lincomb<real>((real*)zq, (const real*)t4, 1.0, dt, (int64_t)n4, s)) ||
-            (st > 0 && (e = launch_lincomb<real>((real*)v, (const real*)zq, kRkA[st], kRkB[st - 1], (int64_t)n4, s))))
+        // z_q += dt t4; for the next reversed stage v = z_r + b_{k-1} z_q with z_r = a_k v
+        if ((e = launch_back_update<real>((real*)zq, (real*)v, (const real*)t4, dt, kRkA[st], st > 0 ? kRkB[st - 1] : 0.0,
+                                          st > 0, (int64_t)n4, s)))
           return fail(BBWADG_EHIP, "adjoint bookkeeping: %s", hipGetErrorString((hipError_t)e));
       }
     }
