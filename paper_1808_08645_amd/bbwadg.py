@@ -31,6 +31,9 @@ EXPORTS = (
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply",
+    "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
+    "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
+    "bbwadg_sur_train_step",
     "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
@@ -103,6 +106,15 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_receiver_elements": (C.c_int, [vp, C.POINTER(C.c_int32)]),
         "bbwadg_misfit_gradient": (C.c_int, [vp, vp, dbl, dbl, i32, vp, i32, vp, pd, vp, vp]),
         "bbwadg_adjoint_apply": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
+        "bbwadg_sur_destroy": (C.c_int, [vp]),
+        "bbwadg_sur_num_params": (C.c_int64, [vp]),
+        "bbwadg_sur_layout": (C.c_int, [vp, i32, C.POINTER(C.c_int32)]),
+        "bbwadg_sur_get_params": (C.c_int, [vp, vp]),
+        "bbwadg_sur_set_params": (C.c_int, [vp, vp]),
+        "bbwadg_sur_forward": (C.c_int, [vp, vp, i32, vp, vp]),
+        "bbwadg_sur_loss_grad": (C.c_int, [vp, vp, vp, i32, pd, vp, vp]),
+        "bbwadg_sur_train_step": (C.c_int, [vp, vp, vp, i32, C.c_float, pd, vp]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }

@@ -50,11 +50,11 @@ def build(verbose: bool = False, jobs: int | None = None, defines=(), out: str |
         obj = os.path.join(build_dir, u.replace(".hip", ".o"))
         cmds.append([hipcc, "-x", "hip", f"--offload-arch={ARCH}", *COMMON, *[f"-D{d}" for d in defines], "-c",
                      os.path.join(CSRC, u), "-o", obj])
-    host_obj = os.path.join(build_dir, "host.o")
-    cmds.append([hipcc, "-x", "c++", *[c for c in COMMON if c not in ("-Xclang", "-target-feature",
-                                                                       "-packed-fp32-ops")],
-                 f"-I{_rocm()}/include", "-D__HIP_PLATFORM_AMD__",
-                 "-c", os.path.join(CSRC, "host.cpp"), "-o", host_obj])
+    for u in sorted(f for f in os.listdir(CSRC) if f.endswith(".cpp")):  # host code
+        cmds.append([hipcc, "-x", "c++", *[c for c in COMMON if c not in ("-Xclang", "-target-feature",
+                                                                           "-packed-fp32-ops")],
+                     f"-I{_rocm()}/include", "-D__HIP_PLATFORM_AMD__",
+                     "-c", os.path.join(CSRC, u), "-o", os.path.join(build_dir, u.replace(".cpp", ".o"))])
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         for err in ex.map(_run, cmds):

@@ -18,6 +18,8 @@
 #include "../../include/bbwadg.h"
 #include "bbwadg_internal.hpp"
 
+#include "surrogate_internal.hpp"
+
 using namespace bbw;
 typedef long double ld;
 
@@ -25,13 +27,18 @@ namespace {
 
 thread_local std::string g_err;
 
-int fail(int code, const char* fmt, ...) {
+int vfail(int code, const char* fmt, va_list ap) {
   char buf[512];
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  g_err = buf;
+  return code;
+}
+
+int fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vfail(code, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return code;
 }
 
@@ -242,6 +249,14 @@ void build_tables(int N, int M, HostTables& T) {
 }
 
 }  // namespace
+
+int bbw::set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vfail(code, fmt, ap);
+  va_end(ap);
+  return code;
+}
 
 // ------------------------------------------------------------------------ context
 struct bbwadg_ctx {

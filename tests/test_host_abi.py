@@ -29,8 +29,9 @@ def bb():
 
 
 def test_library_exports_every_declared_symbol(bb):
-    header = open(os.path.join(ROOT, "include", "bbwadg.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|int32_t|const char\*)\s+(bbwadg_\w+)\s*\(", header, re.M))
+    inc = os.path.join(ROOT, "include")
+    header = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
+    declared = set(re.findall(r"^\s*(?:int|int32_t|int64_t|const char\*)\s+(bbwadg_\w+)\s*\(", header, re.M))
     assert declared, "no declarations parsed"
     lib = C.CDLL(bb.LIB_PATH)
     for name in declared:
