@@ -344,6 +344,88 @@ def adjoint_bench(nsteps=500, ckpt=50, n_fd=20):
     return out
 
 
+def surrogate_bench(n_models=256, n_train=224, nsteps=400, train_steps=4000, batch=32):
+    """Trace surrogate on 16^3 x 6 = 24,576 tets, N=4, M=2 (rigid walls, 64 receivers on the top
+    face, Gaussian pulse at (0.5, 0.5, 0.85), nsteps steps at one dt for every medium): BBWADG
+    makes the traces of n_models seeded media (FP64), the surrogate trains on n_train of them
+    (Adam, cosine learning rate 1e-3 -> 1e-5) and is judged by BBWADG on the rest."""
+    import time
+
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from paper_1808_08645_amd.surrogate import Surrogate
+    from workloads import c2_random_model, grid_centres, ic_gaussian_pulse, kuhn_cube_mesh, receiver_grid
+    xyz, etov = kuhn_cube_mesh(16)
+    s = bb.Solver(xyz, etov, 4, 2, dtype="f64", bc="rigid")
+    s.set_receivers(receiver_grid(8, 1.0))
+    pulse = lambda x, y, z: ic_gaussian_pulse(x, y, z, centre=(0.5, 0.5, 0.85), width=0.1)  # noqa: E731
+    zero = lambda x, y, z: 0.0 * x  # noqa: E731
+    q = s.to_device(s.initial_state([pulse, zero, zero, zero]))
+    s.project_c2(lambda x, y, z: 4.0 + 0.0 * x)
+    dt = s.suggest_dt(0.5)
+    gx, gy, gz = grid_centres(16)
+    X = np.zeros((n_models, 16, 16, 16), dtype=np.float32)
+    Y = np.zeros((n_models, nsteps * 64), dtype=np.float32)
+    t_solver = 0.0
+    for i in range(n_models):
+        f = c2_random_model(i)
+        X[i] = f(gx, gy, gz)
+        s.project_c2(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, tr = s.misfit_gradient(q, dt, nsteps, None, gradient=False)
+        torch.cuda.synchronize()
+        t_solver += time.perf_counter() - t0
+        Y[i] = tr.cpu().numpy().ravel()
+        if i % 64 == 63:
+            print(json.dumps({"surrogate_progress": f"{i + 1} media simulated"}), file=sys.stderr, flush=True)
+    xin = (X - 2.5) / 1.5
+    sigma = float(Y[:n_train].std())
+    yt = Y / sigma
+    sur = Surrogate(nsteps * 64, batch, seed=1)
+    xd = torch.tensor(xin, device="cuda")
+    yd = torch.tensor(yt, device="cuda")
+    rng = np.random.default_rng(2)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(train_steps):
+        idx = torch.tensor(rng.choice(n_train, batch, replace=False), device="cuda")
+        lr = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + np.cos(np.pi * k / train_steps))
+        losses.append(sur.train_step(xd[idx], yd[idx], lr))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    # judge on the held-out media
+    test = np.arange(n_train, n_models)
+    preds = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a in range(0, len(test), batch):
+        preds.append(sur.forward(xd[test[a:a + batch]]))
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    P = torch.cat(preds).cpu().numpy() * sigma
+    T = Y[test]
+    err = np.linalg.norm(P - T, axis=1) / np.linalg.norm(T, axis=1)
+    mean_pred = Y[:n_train].mean(0)
+    err_mean = np.linalg.norm(mean_pred[None] - T, axis=1) / np.linalg.norm(T, axis=1)
+    Ptr = []
+    for a in range(0, n_train, batch):
+        Ptr.append(sur.forward(xd[a:min(n_train, a + batch)]))
+    Ptr = torch.cat(Ptr).cpu().numpy() * sigma
+    err_train = np.linalg.norm(Ptr - Y[:n_train], axis=1) / np.linalg.norm(Y[:n_train], axis=1)
+    return {"elements": int(etov.shape[0]), "N": 4, "M": 2, "receivers": 64, "steps": nsteps, "dt": dt,
+            "media": n_models, "train": n_train, "held_out": int(len(test)), "parameters": sur.num_params,
+            "train_steps": train_steps, "batch": batch, "loss_first_last": [losses[0], losses[-1]],
+            "held_out_rel_l2": {"mean": float(err.mean()), "median": float(np.median(err)), "max": float(err.max())},
+            "train_rel_l2_mean": float(err_train.mean()),
+            "mean_trace_predictor_rel_l2_mean": float(err_mean.mean()),
+            "accepted_below_0.2": int((err < 0.2).sum()), "fallback_to_bbwadg": int((err >= 0.2).sum()),
+            "bbwadg_s_per_medium": t_solver / n_models, "surrogate_s_per_medium": t_inf / len(test),
+            "train_s": t_train}
+
+
 def c2_bumps_medium():
     from workloads import c2_gaussian_bumps
     return c2_gaussian_bumps(0)
@@ -369,6 +451,10 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the default workload: misfit gradient on 82,944 tets, N=4, M=2, 500 steps")
     ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--surrogate", action="store_true",
+                    help="instead of the default workload: train and judge the trace surrogate (256 media)")
+    ap.add_argument("--surrogate-media", type=int, default=256)
+    ap.add_argument("--surrogate-train-steps", type=int, default=4000)
     ap.add_argument("--fd", type=int, default=20, help="finite-difference checks of the adjoint gradient")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -384,6 +470,12 @@ def main():
         res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
         print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
+        return
+    if args.surrogate:
+        nm = args.surrogate_media
+        res = surrogate_bench(nm, nm - max(1, nm // 8), train_steps=args.surrogate_train_steps)
+        print(json.dumps({"workload": "surrogate: cube 16^3x6, N=4, M=2, 64 receivers x 400 steps, 256 media",
+                          "data": "synthetic", "surrogate": res}), flush=True)
         return
     if args.adjoint:
         res = adjoint_bench(args.adjoint_steps, 50, args.fd)

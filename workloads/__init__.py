@@ -34,6 +34,8 @@ __all__ = [
     "manufactured_solution",
     "manufactured_source",
     "receiver_grid",
+    "c2_random_model",
+    "grid_centres",
     "random_state",
     "random_c2_coefficients",
     "dim_p",
@@ -204,6 +206,46 @@ def manufactured_source(c2):
     def g(x, y, z):
         return (3.0 - 1.0 / c2(x, y, z)) * np.pi * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
     return g
+
+
+def c2_random_model(seed: int, transition: float = 0.03):
+    """A seeded velocity model with c^2 in [1, 4]: 2-4 layers split by parallel planes with a
+    tilted normal (a, b, 1)/|.|, a, b ~ U[-0.3, 0.3], interface offsets ~ U over the cube's
+    extent along the normal, layer values ~ U[1, 3.5], each interface a tanh step of the given
+    width (0.03 keeps the degree-2 projection on the 16^3 Kuhn mesh positive: sharp jumps of
+    this size make it negative in about one medium in five); plus 4 Gaussian bumps (amplitude
+    U[-0.5, 0.5], width U[0.08, 0.2], centres U[0, 1]^3); clipped to [1, 4]."""
+    rng = np.random.default_rng(10_000 + int(seed))
+    a, b = rng.uniform(-0.3, 0.3, size=2)
+    nrm = np.array([a, b, 1.0])
+    nrm /= np.linalg.norm(nrm)
+    corners = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=float) @ nrm
+    nl = int(rng.integers(2, 5))
+    cuts = np.sort(rng.uniform(corners.min(), corners.max(), size=nl - 1))
+    vals = rng.uniform(1.0, 3.5, size=nl)
+    amp = rng.uniform(-0.5, 0.5, size=4)
+    wid = rng.uniform(0.08, 0.2, size=4)
+    ctr = rng.uniform(0.0, 1.0, size=(4, 3))
+
+    def f(x, y, z):
+        x, y, z = np.broadcast_arrays(np.asarray(x, dtype=np.float64), y, z)
+        d = nrm[0] * x + nrm[1] * y + nrm[2] * z
+        out = vals[0] + np.zeros_like(d)
+        for i, ct in enumerate(cuts):
+            out = out + (vals[i + 1] - vals[i]) * 0.5 * (1.0 + np.tanh((d - ct) / transition))
+        for A, w, c in zip(amp, wid, ctr):
+            out = out + A * np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2.0 * w * w))
+        return np.clip(out, 1.0, 4.0)
+
+    return f
+
+
+def grid_centres(n: int = 16):
+    """Cell centres ((i + 1/2)/n) of an n^3 grid on the unit cube as (x, y, z) arrays of shape
+    [n, n, n] indexed [z, y, x]."""
+    c = (np.arange(n) + 0.5) / n
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    return x, y, z
 
 
 def receiver_grid(n: int = 8, z: float = 1.0, shift=(0.5, 0.53125)):
