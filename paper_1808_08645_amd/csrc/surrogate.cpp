@@ -52,6 +52,8 @@ struct bbwadg_sur {
   std::vector<float*> act, dy, dcol;    // per layer
   std::vector<uint16_t*> actbf, col;    // per layer
   uint16_t* dybf = nullptr;
+  float* part = nullptr;        // split-K partial sums
+  int64_t part_size = 0;
   double* partial = nullptr;
   int nred = 256;
   int64_t step = 0;
@@ -70,6 +72,23 @@ struct bbwadg_sur {
 };
 
 namespace {
+
+// Split K when the output has few 64 x 64 blocks and K is long: at most kMaxSplit slices of
+// at least 256, into the context's partial-sum scratch.
+constexpr int kMaxSplit = 64;
+
+void choose_split(bbwadg_sur* s, GemmArgs& g) {
+  const int64_t blocks = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  int64_t S = 1;
+  if (blocks < 128 && g.K >= 512) S = std::min<int64_t>({kMaxSplit, g.K / 256, (512 + blocks - 1) / blocks});
+  while (S > 1 && S * g.M * g.N > s->part_size) --S;
+  if (S > 1) {
+    g.ksplit = (int32_t)S;
+    g.kc = ((g.K + S - 1) / S + 15) / 16 * 16;
+    g.ksplit = (int32_t)((g.K + g.kc - 1) / g.kc);
+    g.part = s->part;
+  }
+}
 
 int forward(bbwadg_sur* s, const float* x, int B, hipStream_t st) {
   int rc;
@@ -98,6 +117,7 @@ int forward(bbwadg_sur* s, const float* x, int B, hipStream_t st) {
     g.sbn = 1;
     g.ldc = y.N;
     g.relu = y.relu;
+    choose_split(s, g);
     if ((rc = kc(sur_gemm(g, st), "gemm"))) return rc;
     in = s->actbf[l];
   }
@@ -128,6 +148,7 @@ int backward(bbwadg_sur* s, int B, hipStream_t st) {
     g.M = y.Kp;
     g.N = y.N;
     g.K = rows;
+    choose_split(s, g);
     if ((rc = kc(sur_gemm(g, st), "gemm dW"))) return rc;
     if (l == 0) break;
     // dX = dY W^T: into the previous layer's output gradient (through col2im for a convolution)
@@ -143,6 +164,7 @@ int backward(bbwadg_sur* s, int B, hipStream_t st) {
     h.K = y.N;
     h.C = y.conv ? s->dcol[l] : s->dy[l - 1];
     h.ldc = y.Kp;
+    choose_split(s, h);
     if ((rc = kc(sur_gemm(h, st), "gemm dX"))) return rc;
     if (y.conv && (rc = kc(sur_col2im(s->dcol[l], s->dy[l - 1], B, y.D, y.Cin, y.Do, (int)y.Kp, st), "col2im")))
       return rc;
@@ -259,7 +281,9 @@ int bbwadg_sur_create(int32_t grid, int32_t nout, int32_t max_batch, uint64_t se
     s->dcol.push_back(dc);
     maxdy = std::max(maxdy, n);
   }
-  if ((rc = s->alloc((void**)&s->dybf, maxdy * 2)) || (rc = bbwadg_sur_set_params(s, w.data()))) {
+  s->part_size = (int64_t)1 << 22;  // 16 MB of partial sums
+  if ((rc = s->alloc((void**)&s->dybf, maxdy * 2)) || (rc = s->alloc((void**)&s->part, (size_t)s->part_size * 4)) ||
+      (rc = bbwadg_sur_set_params(s, w.data()))) {
     delete s;
     return rc;
   }

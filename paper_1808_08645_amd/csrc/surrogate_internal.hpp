@@ -19,6 +19,9 @@ struct GemmArgs {
   int64_t M, N, K;
   int64_t sam, sak, sbk, sbn, ldc;
   int32_t accumulate, relu;
+  int32_t ksplit;       // > 1: K in slices of kc (multiple of 16), partial blocks in part
+  int64_t kc;
+  float* part;          // [ksplit][M][N] scratch
 };
 
 int sur_gemm(const GemmArgs& g, void* stream);

@@ -23,6 +23,9 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 // C[m][n] (=|+=) act(sum_k A(m,k) B(k,n) + bias[n]); A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn].
 // One wavefront computes a 32 x 32 block of C as 2 x 2 MFMA tiles; a workgroup holds 4 waves
 // (a 64 x 64 block).
+// With g.ksplit > 1, workgroup z sums the K range [z kc, (z+1) kc) (kc a multiple of 16) and
+// writes its raw partial block to part[z][M][N]; splitk_reduce_kernel adds the slices in order
+// and applies the epilogue.
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
@@ -34,7 +37,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
+  const int64_t kb = g.ksplit > 1 ? (int64_t)blockIdx.z * g.kc : 0;
+  const int64_t ke = g.ksplit > 1 ? (kb + g.kc < g.K ? kb + g.kc : g.K) : g.K;
+  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
     s4 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -42,7 +47,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t k = k0 + 4 * kq + j;
-        const bool ka = k < g.K;
+        const bool ka = k < ke;
         a[i][j] = (short)((ka && m < g.M) ? g.A[m * g.sam + k * g.sak] : 0);
         b[i][j] = (short)((ka && n < g.N) ? g.B[k * g.sbk + n * g.sbn] : 0);
       }
@@ -59,7 +64,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t m = m0 + 16 * i + 4 * kq + e, n = n0 + 16 * j + r;
-        if (m < g.M && n < g.N) {
+        if (m < g.M && n < g.N && g.ksplit > 1) {
+          g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][e];
+        } else if (m < g.M && n < g.N) {
           float v = acc[i][j][e];
           float* c = g.C + m * g.ldc + n;
           if (g.accumulate) v += *c;
@@ -69,6 +76,21 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
           if (g.Cbf) g.Cbf[m * g.ldc + n] = to_bf16(v);
         }
       }
+}
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
+  const int64_t total = g.M * g.N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = i / g.N, n = i - m * g.N;
+    float v = 0.f;
+    for (int z = 0; z < g.ksplit; ++z) v += g.part[(int64_t)z * total + i];
+    float* c = g.C + m * g.ldc + n;
+    if (g.accumulate) v += *c;
+    if (g.bias) v += g.bias[n];
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    *c = v;
+    if (g.Cbf) g.Cbf[m * g.ldc + n] = to_bf16(v);
+  }
 }
 
 __global__ __launch_bounds__(256) void cast_bf16_kernel(const float* x, uint16_t* y, int64_t n) {
@@ -131,13 +153,20 @@ __global__ __launch_bounds__(256) void relu_bwd_kernel(float* dy, const float* a
     if (!(a[i] > 0.f)) dy[i] = 0.f;
 }
 
-// db[n] = sum_m dy[m][n], one thread per column, rows in order (deterministic).
+// db[n] = sum_m dy[m][n]: one workgroup per column, rows strided over its threads, then a
+// fixed-order tree (deterministic).
 __global__ __launch_bounds__(256) void colsum_kernel(const float* dy, float* db, int64_t M, int64_t N) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+  __shared__ float red[256];
+  const int64_t n = blockIdx.x;
   float s = 0.f;
-  for (int64_t m = 0; m < M; ++m) s += dy[m * N + n];
-  db[n] = s;
+  for (int64_t m = threadIdx.x; m < M; m += 256) s += dy[m * N + n];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[n] = red[0];
 }
 
 // Mean squared error over n values: per-block partial sums of (p - t)^2 in FP64 and the
@@ -185,8 +214,13 @@ int last() { return (int)hipGetLastError(); }
 
 int sur_gemm(const GemmArgs& g, void* s) {
   if (g.M <= 0 || g.N <= 0) return 0;
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)(g.ksplit > 1 ? g.ksplit : 1));
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, (hipStream_t)s, g);
+  if (g.ksplit > 1) {
+    int e = last();
+    if (e) return e;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid1(g.M * g.N)), dim3(256), 0, (hipStream_t)s, g);
+  }
   return last();
 }
 int sur_cast_bf16(const float* x, uint16_t* y, int64_t n, void* s) {
@@ -211,7 +245,7 @@ int sur_relu_bwd(float* dy, const float* a, int64_t n, void* s) {
 }
 int sur_colsum(const float* dy, float* db, int64_t M, int64_t N, void* s) {
   if (N <= 0) return 0;
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)s, dy, db, M, N);
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)N), dim3(256), 0, (hipStream_t)s, dy, db, M, N);
   return last();
 }
 int sur_mse(const float* p, const float* t, float* dp, double* partial, int64_t n, int nblocks, void* s) {
