@@ -173,3 +173,24 @@ def test_adjoint_error_paths(bb):
         s.misfit_gradient(q, 0.01, 3, checkpoint_every=0)
     with pytest.raises(bb.BBWADGError):
         s.misfit_gradient(q, 0.01, 3, np.full((3, 1), np.nan))
+
+
+def test_full_size_adjoint_pairing_identity(bb):
+    """82,944 tets, N=4, M=2 (the adjoint workload's size), rigid walls: the pairing identity
+    (A x, S z) = (x, S B W z) in L^2 for random states holds at full size."""
+    print("[adjoint pairing full size]", flush=True)
+    xyz, etov = kuhn_cube_mesh(24)
+    s = bb.Solver(xyz, etov, 4, 2, bc="rigid")
+    s.set_c2(random_c2_coefficients(81, s.K, s.Mp))
+    x = s.to_device(random_state(82, s.K, s.Np))
+    z = s.to_device(random_state(83, s.K, s.Np))
+    ax, bwz = s.rhs(x), s.adjoint_apply(z)
+
+    def inner(a, b):
+        return (s.l2norm2((a + b).contiguous()) - s.l2norm2((a - b).contiguous())) / 4.0
+
+    sign = np.array([1.0, -1.0, -1.0, -1.0])
+    lhs, rhs = float(np.dot(sign, inner(ax, z))), float(np.dot(sign, inner(x, bwz)))
+    scale = float(np.sum(np.sqrt(s.l2norm2(ax) * s.l2norm2(z)) + np.sqrt(s.l2norm2(x) * s.l2norm2(bwz))))
+    print(f"  rel {abs(lhs - rhs) / scale:.2e}", flush=True)
+    assert abs(lhs - rhs) < 1e-12 * scale, (lhs, rhs)

@@ -154,3 +154,33 @@ def test_source_error_paths(bb):
         s.set_source(np.ones((s.K, s.Np)), omega=np.inf)
     with pytest.raises(ValueError):
         s.set_source(np.ones((s.K, s.Np + 1)))
+
+
+def test_full_size_rhs_with_source_on_sampled_elements(bb):
+    """196,608 tets, N=5, M=2 (the benchmark's launch configuration) with the manufactured
+    source at t = 0.3: the oracle recomputes 200 sampled elements with their face neighbours."""
+    print("[full-size source]", flush=True)
+    xyz, etov = kuhn_cube_mesh(32)
+    s = bb.Solver(xyz, etov, 5, 2)
+    s.project_c2(c2_sinusoid)
+    g = manufactured_source(c2_sinusoid)
+    s.set_source(g, amp=1.2, omega=np.pi)
+    q = random_state(71, s.K, s.Np)
+    out = s.rhs(s.to_device(q), t=0.3).cpu().numpy()
+    rng = np.random.default_rng(72)
+    seeds = np.unique(np.concatenate([rng.choice(s.K, 196, replace=False), [0, s.K - 1]]))
+    nbr = s.geometry()["nbr"]
+    sub = set(int(k) for k in seeds)
+    for k in seeds:
+        sub.update(int(v) >> 2 for v in nbr[k] if v >= 0)
+    sub = np.array(sorted(sub))
+    o = Oracle(xyz, etov[sub], 5, 2)
+    o.set_c2_function(c2_sinusoid, project=True)
+    o.set_source(g, amp=1.2, omega=np.pi)
+    R = o.rhs(o.from_bernstein(q[:, sub]), t=0.3)
+    pos = np.searchsorted(sub, seeds)
+    a = o.bernstein_values_at_quad(out[:, seeds])
+    b = o.values_at_quad(R[:, pos])
+    wJ = o.mesh.J[pos][:, None] * o.wq[None, :]
+    err = np.sqrt(np.sum((a - b) ** 2 * wJ, axis=(1, 2)) / np.sum(b ** 2 * wJ, axis=(1, 2)))
+    assert np.all(err < FP64_TOL), err.max()
