@@ -426,6 +426,55 @@ def surrogate_bench(n_models=256, n_train=224, nsteps=400, train_steps=4000, bat
             "train_s": t_train}
 
 
+def elastic_bench(reps=20):
+    """Elastic weight-adjusted update (9 fields, isotropic media projected to P^M), N = 2..9,
+    M = 1, 2, on the 11^3 x 6 = 7,986-tet mesh (about the size of the paper's 7,854-element timing
+    mesh) and on the 196,608-tet mesh: time per launch and per element, FP64 and FP32, next to
+    nine dense quadrature updates (the cost of the same update by quadrature WADG)."""
+    import torch
+
+    import paper_1808_08645_amd as bb
+    from workloads import c2_gaussian_bumps, c2_sinusoid, kuhn_cube_mesh
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = []
+    for cells in (11, 32):
+        xyz, etov = kuhn_cube_mesh(cells)
+        for n in range(2, 10):
+            for m in (1, 2):
+                e = {"elements": int(etov.shape[0]), "N": n, "M": m}
+                for dtype in ("f64", "f32"):
+                    s = bb.Solver(xyz, etov, n, m, dtype=dtype)
+                    s.elastic_set_media(lambda x, y, z: 1.0 / (1.0 + 0.3 * x), c2_gaussian_bumps(0),
+                                        lambda x, y, z: 0.5 * c2_sinusoid(x, y, z))
+                    wt = torch.float64 if dtype == "f64" else torch.float32
+                    r = torch.randn((9, s.K, s.Np), dtype=wt, device="cuda")
+                    o = torch.empty_like(r)
+                    ms = timed(lambda: s.elastic_update(r, o))
+                    e[dtype] = {"ms": ms, "us_per_element": ms * 1e3 / s.K}
+                    if dtype == "f64":
+                        s.project_c2(c2_gaussian_bumps(0))
+                        s.dense_set_c2(None)
+                        p0 = r[0].contiguous()
+                        p1 = torch.empty_like(p0)
+                        e["dense_9_updates_ms"] = 9 * timed(lambda: s.dense_update(p0, p1))
+                    del s, r, o
+                out.append(e)
+                print(json.dumps({"elastic_progress": e}), file=sys.stderr, flush=True)
+                torch.cuda.empty_cache()
+    return out
+
+
 def c2_bumps_medium():
     from workloads import c2_gaussian_bumps
     return c2_gaussian_bumps(0)
@@ -454,6 +503,8 @@ def main():
     ap.add_argument("--surrogate", action="store_true",
                     help="instead of the default workload: train and judge the trace surrogate (256 media)")
     ap.add_argument("--surrogate-media", type=int, default=256)
+    ap.add_argument("--elastic", action="store_true",
+                    help="instead of the default workload: elastic weight-adjusted update times, N = 2..9, M = 1, 2")
     ap.add_argument("--surrogate-train-steps", type=int, default=4000)
     ap.add_argument("--fd", type=int, default=20, help="finite-difference checks of the adjoint gradient")
     args = ap.parse_args()
@@ -470,6 +521,11 @@ def main():
         res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
         print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
+        return
+    if args.elastic:
+        res = elastic_bench(max(1, min(args.steps, 50)))
+        print(json.dumps({"workload": "elastic update: cubes 11^3x6 and 32^3x6, N=2..9, M=1,2", "unit": "ms per update",
+                          "data": "synthetic", "elastic": res}), flush=True)
         return
     if args.surrogate:
         nm = args.surrogate_media

@@ -276,6 +276,25 @@ int bbwadg_misfit_gradient(bbwadg_ctx* ctx, const void* q0, double t0, double dt
  * overlap). Allocates two state-sized temporaries; synchronises `stream`. */
 int bbwadg_adjoint_apply(bbwadg_ctx* ctx, const void* z, void* out, void* stream);
 
+/* ---- elastic weight-adjusted update (paper Section 2.2, eq. ewadg) ----------------------
+ * The velocity-stress system rho v_t = sum_i A_i^T d sigma/dx_i, C^{-1} sigma_t = sum_i A_i
+ * dv/dx_i with isotropic C (Lame parameters lambda, mu). Its weighted mass matrices are
+ * replaced by the weight-adjusted inverse (I (x) M^{-1}) M_C (I (x) M^{-1}) (and M_{1/rho}
+ * for the velocity), applied with the context's N, M and telescoped projection. */
+
+/* Media: host FP64 Bernstein coefficients [K][Mp] of degree M of 1/rho, lambda and mu (e.g.
+ * projections from bbwadg_project_samples with degree M), copied. EINVAL if not finite. */
+int bbwadg_elastic_set_media(bbwadg_ctx* ctx, const double* rho_inv, const double* lam, const double* mu);
+
+/* out = the weight-adjusted update of the DG right-hand side r, both device [9][K][Np] of the
+ * context dtype (v1, v2, v3, sigma_xx, yy, zz, yz, xz, xy), no overlap:
+ *   out_v_i = Pi_N(rho^{-1} r_v_i),  out_sigma_i = Pi_N(lambda tr r_sigma + 2 mu r_sigma_i)
+ *   (i = xx, yy, zz),  out_sigma_s = Pi_N(mu r_sigma_s)  (s = yz, xz, xy),
+ * each product exact in degree N + M (eq. mcoeff) and each Pi_N the telescoped projection
+ * (Theorem 5.1): 12 products and 9 scalar projections per element. EC2 before
+ * bbwadg_elastic_set_media. */
+int bbwadg_elastic_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
+
 /* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
  * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
  * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */

@@ -30,7 +30,7 @@ EXPORTS = (
     "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
-    "bbwadg_misfit_gradient", "bbwadg_adjoint_apply",
+    "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
     "bbwadg_sur_train_step",
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_receiver_elements": (C.c_int, [vp, C.POINTER(C.c_int32)]),
         "bbwadg_misfit_gradient": (C.c_int, [vp, vp, dbl, dbl, i32, vp, i32, vp, pd, vp, vp]),
         "bbwadg_adjoint_apply": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_elastic_set_media": (C.c_int, [vp, pd, pd, pd]),
+        "bbwadg_elastic_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
         "bbwadg_sur_destroy": (C.c_int, [vp]),
         "bbwadg_sur_num_params": (C.c_int64, [vp]),
@@ -346,6 +348,33 @@ class Solver:
         self._check_state(out, "out")
         _check(self._lib.bbwadg_adjoint_apply(self._ctx, C.c_void_p(z.data_ptr()), C.c_void_p(out.data_ptr()),
                                               self._stream()))
+        return out
+
+    # ------------------------------------------------------------------ elastic update
+    def elastic_set_media(self, rho_inv, lam, mu):
+        """Isotropic media as degree-M Bernstein coefficients [K, Mp] (or vectorised functions,
+        projected onto P^M here) of 1/rho, lambda and mu."""
+        arrs = []
+        for f in (rho_inv, lam, mu):
+            a = self.project_function(f, self.M) if callable(f) else np.ascontiguousarray(f, dtype=np.float64)
+            if a.shape != (self.K, self.Mp):
+                raise ValueError(f"media coefficients must be [{self.K}, {self.Mp}]")
+            arrs.append(a)
+        _check(self._lib.bbwadg_elastic_set_media(self._ctx, *[_dptr(a) for a in arrs]))
+        return arrs
+
+    def elastic_update(self, r, out=None):
+        """Weight-adjusted update of the 9 elastic fields r [9, K, Np] (device)."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        for t, name in ((r, "r"), (out, "out")):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want or
+                                  tuple(t.shape) != (9, self.K, self.Np) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous device {want} tensor of shape (9, {self.K}, {self.Np})")
+        if out is None:
+            out = torch.empty_like(r)
+        _check(self._lib.bbwadg_elastic_update(self._ctx, C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
+                                               self._stream()))
         return out
 
     def suggest_dt(self, cfl: float) -> float:

@@ -78,6 +78,21 @@ struct DenseArgs {
 };
 int launch_wadg_dense(int N, const DenseArgs& a, void* stream);
 
+// Weight-adjusted update of the 9 elastic fields (elastic_kernel.hip): r, out [9][K][Np]
+// (v1, v2, v3, sigma xx, yy, zz, yz, xz, xy); weights [K][Mp] as Bernstein coefficients.
+template <typename real>
+struct ElasticArgs {
+  const real* r;
+  real* out;
+  const real* rho_inv;
+  const real* lam;
+  const real* mu;
+  int64_t K;
+  real cj[kMaxN + 1];
+};
+template <typename real>
+int launch_elastic_update(int N, int M, const ElasticArgs<real>& a, void* stream);
+
 // Adjoint helpers (adjoint_kernel.hip); each returns a hipError_t value cast to int.
 // Tables at the dense rule (exact to degree 2N + M), in MFMA operand order as DenseArgs:
 // va = V_q (NQP/16 x NPP/4 x 64) and bwa[qc][ks][lane] = w_q B^M_g(x_q) for

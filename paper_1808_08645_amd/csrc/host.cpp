@@ -313,6 +313,10 @@ struct bbwadg_ctx {
   void* d_rec_kvec = nullptr;
   void* d_adj_bwa = nullptr;    // rule weight times B^M at the dense points, MFMA operand order
   void* d_adj_ones = nullptr;   // [K] ones (dtype): c^2 = 1 for the plain DG operator
+  // elastic media (isotropic): Bernstein coefficients of degree M, dtype
+  void* d_el_rho = nullptr;     // [K][Mp] 1/rho
+  void* d_el_lam = nullptr;     // [K][Mp] lambda
+  void* d_el_mu = nullptr;      // [K][Mp] mu
 };
 
 namespace {
@@ -343,7 +347,7 @@ void free_device(bbwadg_ctx* c) {
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
                    &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
                    &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_bwa,
-                   &c->d_adj_ones};
+                   &c->d_adj_ones, &c->d_el_rho, &c->d_el_lam, &c->d_el_mu};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -1457,6 +1461,61 @@ int bbwadg_misfit_gradient(bbwadg_ctx* c, const void* q0, double t0, double dt, 
   if (c->dtype == BBWADG_F64)
     return misfit_gradient_typed<double>(c, q0, t0, dt, nsteps, data, checkpoint_every, traces, misfit, grad, s);
   return misfit_gradient_typed<float>(c, q0, t0, dt, nsteps, data, checkpoint_every, traces, misfit, grad, s);
+}
+
+int bbwadg_elastic_set_media(bbwadg_ctx* c, const double* rho_inv, const double* lam, const double* mu) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!rho_inv || !lam || !mu) return fail(BBWADG_EINVAL, "NULL medium array");
+  const size_t n = (size_t)c->K * c->Mp;
+  const double* src[3] = {rho_inv, lam, mu};
+  void** dst[3] = {&c->d_el_rho, &c->d_el_lam, &c->d_el_mu};
+  for (int f = 0; f < 3; ++f)
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(src[f][i])) return fail(BBWADG_EINVAL, "medium %d coefficient %zu not finite", f, i);
+  for (int f = 0; f < 3; ++f) {
+    if (!*dst[f] && (rc = dmalloc(dst[f], n * c->rsz))) return rc;
+    if (c->dtype == BBWADG_F64) {
+      rc = upload(*dst[f], src[f], n * 8);
+    } else {
+      std::vector<float> v(src[f], src[f] + n);
+      rc = upload(*dst[f], v.data(), n * 4);
+    }
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int bbwadg_elastic_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!r || !out) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (r == out) return fail(BBWADG_EINVAL, "r and out must not overlap");
+  if (!c->d_el_rho) return fail(BBWADG_EC2, "elastic media not set (call bbwadg_elastic_set_media)");
+  int e;
+  if (c->dtype == BBWADG_F64) {
+    ElasticArgs<double> a{};
+    a.r = (const double*)r;
+    a.out = (double*)out;
+    a.rho_inv = (const double*)c->d_el_rho;
+    a.lam = (const double*)c->d_el_lam;
+    a.mu = (const double*)c->d_el_mu;
+    a.K = c->K;
+    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = c->tables.cj[j];
+    e = launch_elastic_update<double>(c->N, c->M, a, stream);
+  } else {
+    ElasticArgs<float> a{};
+    a.r = (const float*)r;
+    a.out = (float*)out;
+    a.rho_inv = (const float*)c->d_el_rho;
+    a.lam = (const float*)c->d_el_lam;
+    a.mu = (const float*)c->d_el_mu;
+    a.K = c->K;
+    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (float)c->tables.cj[j];
+    e = launch_elastic_update<float>(c->N, c->M, a, stream);
+  }
+  if (e) return fail(BBWADG_EHIP, "elastic update launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
 }
 
 int bbwadg_adjoint_apply(bbwadg_ctx* c, const void* z, void* out, void* stream) {

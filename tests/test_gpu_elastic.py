@@ -1,0 +1,91 @@
+"""The elastic weight-adjusted update on the device (Bernstein products and telescoped
+projections) against the quadrature oracle, on the same seeded Bernstein inputs."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle.elastic import elastic_update
+from workloads import c2_gaussian_bumps, c2_sinusoid, kuhn_cube_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1808_08645_amd as bb
+    bb.load_library()
+    return bb
+
+
+def _media(K, Mp, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.uniform(0.5, 1.5, (K, Mp)), rng.uniform(0.5, 2.0, (K, Mp)), rng.uniform(0.3, 1.0, (K, Mp)))
+
+
+def _compare(o, out_gpu, ref_modal):
+    a = o.bernstein_values_at_quad(out_gpu.double().cpu().numpy())
+    b = o.values_at_quad(ref_modal)
+    return o.rel_l2(a, b)
+
+
+CASES = [(1, 0), (1, 1), (2, 2), (3, 1), (4, 2), (5, 1), (5, 2), (6, 3), (7, 2), (8, 4), (9, 4)]
+
+
+@pytest.mark.parametrize("N,M", CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_elastic_update_matches_oracle(bb, N, M, dtype):
+    print(f"[elastic] N={N} M={M} {dtype}", flush=True)
+    xyz, etov = kuhn_cube_mesh(2)
+    etov = etov[:37]  # a ragged element count
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    K, Np, Mp = s.K, s.Np, s.Mp
+    r = np.random.default_rng(90 + N).standard_normal((9, K, Np))
+    rho_inv, lam, mu = _media(K, Mp, 91 + M)
+    if dtype == "f32":
+        r, rho_inv, lam, mu = (x.astype(np.float32).astype(np.float64) for x in (r, rho_inv, lam, mu))
+    s.elastic_set_media(rho_inv, lam, mu)
+    import torch
+    rd = torch.as_tensor(r, device="cuda").to(torch.float64 if dtype == "f64" else torch.float32).contiguous()
+    out = s.elastic_update(rd)
+    o = Oracle(xyz, etov, N, M)
+    ref = elastic_update(o, o.from_bernstein(r), rho_inv, lam, mu)
+    err = _compare(o, out, ref)
+    tol = 1e-11 if dtype == "f64" else (1e-5 if N <= 7 else 2e-4)
+    assert np.all(err < tol), err
+
+
+def test_elastic_full_size_sampled(bb):
+    """196,608 tets, N=5, M=2, media projected from smooth fields; the oracle checks 300
+    sampled elements (the update is local to an element)."""
+    import torch
+    print("[elastic full size]", flush=True)
+    xyz, etov = kuhn_cube_mesh(32)
+    s = bb.Solver(xyz, etov, 5, 2)
+    rho_inv, lam, mu = s.elastic_set_media(lambda x, y, z: 1.0 / (1.0 + 0.3 * x), c2_gaussian_bumps(0),
+                                           lambda x, y, z: 0.5 * c2_sinusoid(x, y, z))
+    r = np.random.default_rng(95).standard_normal((9, s.K, s.Np))
+    out = s.elastic_update(torch.as_tensor(r, device="cuda").contiguous()).cpu().numpy()
+    sel = np.sort(np.random.default_rng(96).choice(s.K, 300, replace=False))
+    o = Oracle(xyz, etov[sel], 5, 2)
+    ref = elastic_update(o, o.from_bernstein(r[:, sel]), rho_inv[sel], lam[sel], mu[sel])
+    err = o.rel_l2(o.bernstein_values_at_quad(out[:, sel]), o.values_at_quad(ref))
+    assert np.all(err < 1e-11), err
+
+
+def test_elastic_error_paths(bb):
+    import torch
+    print("[elastic errors]", flush=True)
+    xyz, etov = kuhn_cube_mesh(1)
+    s = bb.Solver(xyz, etov, 2, 1)
+    r = torch.zeros((9, s.K, s.Np), dtype=torch.float64, device="cuda")
+    with pytest.raises(bb.BBWADGError) as ei:
+        s.elastic_update(r)
+    assert ei.value.code == -3
+    bad = np.ones((s.K, s.Mp))
+    bad[0, 0] = np.inf
+    with pytest.raises(bb.BBWADGError):
+        s.elastic_set_media(bad, bad * 0 + 1, bad * 0 + 1)
+    with pytest.raises(ValueError):
+        s.elastic_update(torch.zeros((4, s.K, s.Np), dtype=torch.float64, device="cuda"))
