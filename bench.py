@@ -426,7 +426,7 @@ def surrogate_bench(n_models=256, n_train=224, nsteps=400, train_steps=4000, bat
             "train_s": t_train}
 
 
-def elastic_bench(reps=20):
+def elastic_bench(reps=20, only=None):
     """Elastic weight-adjusted update (9 fields, isotropic media projected to P^M), N = 2..9,
     M = 1, 2, on the 11^3 x 6 = 7,986-tet mesh (about the size of the paper's 7,854-element timing
     mesh) and on the 196,608-tet mesh: time per launch and per element, FP64 and FP32, next to
@@ -452,6 +452,8 @@ def elastic_bench(reps=20):
         xyz, etov = kuhn_cube_mesh(cells)
         for n in range(2, 10):
             for m in (1, 2):
+                if only is not None and (cells, n, m) != only:
+                    continue
                 e = {"elements": int(etov.shape[0]), "N": n, "M": m}
                 for dtype in ("f64", "f32"):
                     s = bb.Solver(xyz, etov, n, m, dtype=dtype)
@@ -505,6 +507,7 @@ def main():
     ap.add_argument("--surrogate-media", type=int, default=256)
     ap.add_argument("--elastic", action="store_true",
                     help="instead of the default workload: elastic weight-adjusted update times, N = 2..9, M = 1, 2")
+    ap.add_argument("--elastic-only", type=str, default=None, help="one case CELLS,N,M (profiling)")
     ap.add_argument("--surrogate-train-steps", type=int, default=4000)
     ap.add_argument("--fd", type=int, default=20, help="finite-difference checks of the adjoint gradient")
     args = ap.parse_args()
@@ -523,7 +526,8 @@ def main():
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
         return
     if args.elastic:
-        res = elastic_bench(max(1, min(args.steps, 50)))
+        only = tuple(int(v) for v in args.elastic_only.split(",")) if args.elastic_only else None
+        res = elastic_bench(max(1, min(args.steps, 50)), only)
         print(json.dumps({"workload": "elastic update: cubes 11^3x6 and 32^3x6, N=2..9, M=1,2", "unit": "ms per update",
                           "data": "synthetic", "elastic": res}), flush=True)
         return
