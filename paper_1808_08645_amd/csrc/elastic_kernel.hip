@@ -8,7 +8,8 @@
 // N + M (eq. mcoeff) followed by 9 scalar projections: M one-degree reductions to degree N
 // and the telescoped projection sum_j c_j E^N_{N-j} (E^N_{N-j})^T (Theorem 5.1).
 //
-// One wavefront per element (grid-stride over elements), everything in its LDS slice.
+// One wavefront per element (grid-stride over elements), everything in its LDS slice; the 9
+// components go through the projection in groups (see ElasticLayout).
 // Coefficients are in the graded order of the library, pos(a1, a2, a3) =
 // dimp(s-1) + a3 (2s + 3 - a3)/2 + a2 with s = a1 + a2 + a3, the same position at every
 // degree >= s, so a lane keeps one multi-index per slot across all levels.
@@ -34,75 +35,91 @@ __host__ __device__ constexpr double factd(int n) {
   return r;
 }
 
-template <int N, int M>
-struct ElasticLayout {
-  static constexpr int NP = dimp(N), NH = dimp(N + M), MP = dimp(M);
-  static constexpr int SH = (NH + 63) / 64;  // item slots of the product degree
-  static constexpr int LEV = [] {            // levels r_0 .. r_N of the telescoping
-    int t = 0;
-    for (int j = 0; j <= N; ++j) t += dimp(N - j);
-    return t;
-  }();
-  // X: 9 inputs and the trace, scaled by 1/alpha!; H, T: product and reduction ping-pong
-  static constexpr int OFF_X = 0, OFF_H = 10 * NP, OFF_T = OFF_H + NH, OFF_L = OFF_T + NH, TOTAL = OFF_L + LEV;
-  static constexpr int PTAB = MP * NH;  // byte table pos(gamma - beta), 255 where it does not exist
-  template <typename real>
-  static constexpr int waves() {
-    const int per = TOTAL * (int)sizeof(real);
-    const int room = 61440 - PTAB;
-    return room / per >= 4 ? 4 : (room / per >= 1 ? room / per : 1);
-  }
-};
-
 __host__ __device__ constexpr int lev_base(int N, int j) {  // start of level j (degree N - j)
   int t = 0;
   for (int i = 0; i < j; ++i) t += dimp(N - i);
   return t;
 }
 
-template <typename real, int N, int M, int WPB>
-__global__ __launch_bounds__(64 * WPB) void elastic_update_kernel(ElasticArgs<real> a) {
-  using L = ElasticLayout<N, M>;
-  constexpr int NP = L::NP, NH = L::NH, MP = L::MP, SH = L::SH;
+// Components are processed in groups of G (9, 3 or 1, the largest whose buffers fit): every
+// phase of the projection runs over G x (coefficients) items at once, so a wavefront syncs
+// (1 + M + 2N) times per group instead of per component and the small levels fill more lanes.
+template <typename real, int N, int M>
+constexpr int elastic_tables() {  // product positions (bytes), stencil table (16 B), gamma! kappa
+  return dimp(M) * dimp(N + M) + 16 * dimp(N + M) + (int)sizeof(real) * dimp(N + M);
+}
+template <typename real, int N, int M>
+constexpr int elastic_per_wave(int G) {
+  return (10 * dimp(N) + 3 * dimp(M) + G * (dimp(N + M) + dimp(N + M - 1) + lev_base(N, N + 1))) * (int)sizeof(real);
+}
+// LDS bytes a wavefront's buffers may take when choosing the group size (occupancy against
+// fewer, wider phases).
+#ifndef BBW_EL_WAVE_BYTES
+#define BBW_EL_WAVE_BYTES 8192
+#endif
+
+template <typename real, int N, int M>
+constexpr int elastic_group() {
+  constexpr int T = elastic_tables<real, N, M>();
+  auto fits = [](int G) {
+    const int w = elastic_per_wave<real, N, M>(G);
+    return w <= BBW_EL_WAVE_BYTES && w + T <= 61440;
+  };
+  return fits(9) ? 9 : (fits(3) ? 3 : 1);
+}
+template <typename real, int N, int M>
+constexpr int elastic_waves() {
+  constexpr int room = (61440 - elastic_tables<real, N, M>()) / elastic_per_wave<real, N, M>(elastic_group<real, N, M>());
+  return room >= 4 ? 4 : (room >= 1 ? room : 1);
+}
+
+template <typename real, int N, int M>
+struct ElasticLayout {
+  static constexpr int NP = dimp(N), NH = dimp(N + M), MP = dimp(M), NB = dimp(N + M - 1);
+  static constexpr int LEV = lev_base(N, N + 1);  // levels r_0 .. r_N
+  static constexpr int G = elastic_group<real, N, M>(), WAVES = elastic_waves<real, N, M>();
+  static constexpr int OFF_X = 0, OFF_W = 10 * NP, OFF_A = OFF_W + 3 * MP, OFF_B = OFF_A + G * NH,
+                       OFF_L = OFF_B + G * NB, TOTAL = OFF_L + G * LEV;
+};
+
+template <typename real, int N, int M>
+__global__ __launch_bounds__((64 * ElasticLayout<real, N, M>::WAVES)) void elastic_update_kernel(ElasticArgs<real> a) {
+  using L = ElasticLayout<real, N, M>;
+  constexpr int NP = L::NP, NH = L::NH, MP = L::MP, NB = L::NB, LEV = L::LEV, G = L::G, WPB = L::WAVES;
+  static_assert(NP < 255, "product positions must fit a byte");
   __shared__ real smem[WPB * L::TOTAL];
-  __shared__ uint8_t ptab[L::PTAB];
-  static_assert(dimp(N) < 255, "product positions must fit a byte");
+  __shared__ uint8_t ptab[MP * NH];
+  __shared__ uint4 itab[NH];
+  __shared__ real facH[NH];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   real* const X = smem + wave * L::TOTAL + L::OFF_X;
-  real* const H = smem + wave * L::TOTAL + L::OFF_H;
-  real* const T = smem + wave * L::TOTAL + L::OFF_T;
+  real* const Wt = smem + wave * L::TOTAL + L::OFF_W;
+  real* const A = smem + wave * L::TOTAL + L::OFF_A;
+  real* const B = smem + wave * L::TOTAL + L::OFF_B;
   real* const LV = smem + wave * L::TOTAL + L::OFF_L;
 
-  // per-slot multi-index of item lane + 64 s (graded order), found once
-  int m1[SH], m2[SH], m3[SH];
-#pragma unroll
-  for (int s = 0; s < SH; ++s) {
-    const int item = lane + 64 * s;
+  // ---- per-block tables -------------------------------------------------------------
+  // itab[i] for the multi-index a at graded position i (s = |a|, D(s) = (s+1)(s+2)/2):
+  //   x: pos(a+e1) = i + D(s) + a3 | pos(a+e3) = i + D(s) + s + 2 << 16  (pos(a+e2) = pos(a+e1) + 1)
+  //   y: pos(a-e1) = i - D(s-1) - a3 | pos(a-e2) = i - D(s-1) - a3 - 1 << 16 (0 where a_j = 0)
+  //   z: pos(a-e3) = i - D(s-1) - s - 1 (0 where a3 = 0) | a1 << 16 | a2 << 24;  w: a3 | s << 8
+  constexpr double kappa = factd(N) * factd(M) / factd(N + M);
+  for (int i = threadIdx.x; i < NH; i += 64 * WPB) {
     int d = 0;
-    while (d < N + M && dimp(d) <= item) ++d;  // degree of the item
-    int r = item - dimp(d - 1), a3 = 0;
+    while (d < N + M && dimp(d) <= i) ++d;
+    int r = i - dimp(d - 1), a3 = 0;
     while (a3 < d && r >= d + 1 - a3) r -= d + 1 - a3, ++a3;
-    m3[s] = a3;
-    m2[s] = r;
-    m1[s] = d - a3 - r;
+    const int a2 = r, a1 = d - a3 - r;
+    const int du = (d + 1) * (d + 2) / 2, dd = d * (d + 1) / 2;
+    uint4 t;
+    t.x = (uint32_t)(i + du + a3) | ((uint32_t)(i + du + d + 2) << 16);
+    t.y = (uint32_t)(a1 > 0 ? i - dd - a3 : 0) | ((uint32_t)(a2 > 0 ? i - dd - a3 - 1 : 0) << 16);
+    t.z = (uint32_t)(a3 > 0 ? i - dd - d - 1 : 0) | ((uint32_t)a1 << 16) | ((uint32_t)a2 << 24);
+    t.w = (uint32_t)a3 | ((uint32_t)d << 8);
+    itab[i] = t;
+    facH[i] = real(kappa * factd(N + M - d) * factd(a1) * factd(a2) * factd(a3));
   }
-  // graded-order neighbours of each slot, with D(s) = (s+1)(s+2)/2, s = |a|:
-  //   pos(a+e1) = pos + D(s) + a3, pos(a+e2) = pos(a+e1) + 1, pos(a+e3) = pos + D(s) + s + 2,
-  //   pos(a-e1) = pos - D(s-1) - a3, pos(a-e2) = pos - D(s-1) - a3 - 1, pos(a-e3) = pos - D(s-1) - s - 1
-  int up1[SH], up2[SH], up3[SH], dn1[SH], dn2[SH], dn3[SH];
-#pragma unroll
-  for (int s = 0; s < SH; ++s) {
-    const int i = lane + 64 * s, sa = m1[s] + m2[s] + m3[s];
-    const int du = (sa + 1) * (sa + 2) / 2, dd = sa * (sa + 1) / 2;
-    up1[s] = i + du + m3[s];
-    up2[s] = up1[s] + 1;
-    up3[s] = i + du + sa + 2;
-    dn1[s] = m1[s] > 0 ? i - dd - m3[s] : 0;
-    dn2[s] = m2[s] > 0 ? i - dd - m3[s] - 1 : 0;
-    dn3[s] = m3[s] > 0 ? i - dd - sa - 1 : 0;
-  }
-  // the product table, once per workgroup: ptab[b][i] = pos(gamma_i - beta_b) or 255
-  for (int t = threadIdx.x; t < L::PTAB; t += 64 * WPB) {
+  for (int t = threadIdx.x; t < MP * NH; t += 64 * WPB) {  // ptab[b][i] = pos(gamma_i - beta_b) or 255
     const int b = t / NH, i = t - (t / NH) * NH;
     int d = 0;
     while (d < N + M && dimp(d) <= i) ++d;
@@ -118,159 +135,124 @@ __global__ __launch_bounds__(64 * WPB) void elastic_update_kernel(ElasticArgs<re
     ptab[t] = ok ? (uint8_t)gpos(g1 - b1, g2 - b2, g3 - b3) : (uint8_t)255;
   }
   __syncthreads();
-  // 1/alpha! of the item as a degree-N coefficient, and kappa gamma! as a degree-(N+M) one
-  constexpr double kappa = factd(N) * factd(M) / factd(N + M);
-  real invN[SH], facH[SH];
-#pragma unroll
-  for (int s = 0; s < SH; ++s) {
-    const int sa = m1[s] + m2[s] + m3[s];
-    const double af = factd(m1[s]) * factd(m2[s]) * factd(m3[s]);
-    invN[s] = sa <= N ? real(1.0 / (factd(N - sa) * af)) : real(0);
-    facH[s] = real(kappa * factd(N + M - sa) * af);
-  }
+
+  // one reduction (E^n_{n-1})^T over G components: y_a = [(a0+1) x_a + sum_j (a_j+1) x_{a+e_j}] / n
+  auto reduce = [&](const real* src, int sst, real* dst, int dstr, int n) {
+    const int cnt = dimp(n - 1);
+    const real inv = real(1) / real(n);
+    for (int t = lane; t < G * cnt; t += 64) {
+      const int cl = t / cnt, i = t - cl * cnt;
+      const uint4 e = itab[i];
+      const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - 1 - (int)(e.w >> 8);
+      const real* x = src + cl * sst;
+      const int u1 = e.x & 0xFFFF, u3 = e.x >> 16;
+      dst[cl * dstr + i] =
+          inv * (real(a0 + 1) * x[i] + real(a1 + 1) * x[u1] + real(a2 + 1) * x[u1 + 1] + real(a3 + 1) * x[u3]);
+    }
+    wsync();
+  };
+
   const int64_t stride = (int64_t)gridDim.x * WPB;
   for (int64_t k = (int64_t)blockIdx.x * WPB + wave; k < a.K; k += stride) {
-    // inputs scaled by 1/alpha! (a0 = N - |a| included), and the trace of the normal stresses
+    // inputs scaled by 1/alpha! (a0 = N - |a| included), the trace of the normal stresses, and
+    // the media scaled by 1/beta!
+    for (int i = lane; i < NP; i += 64) {
+      const uint4 e = itab[i];
+      const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, sa = e.w >> 8;
+      const real inv = real(1.0 / (factd(N - sa) * factd(a1) * factd(a2) * factd(a3)));
+      real tr = real(0);
 #pragma unroll
-    for (int s = 0; s < SH; ++s) {
-      const int i = lane + 64 * s;
-      if (s * 64 < NP && i < NP) {
-        const real inv = invN[s];
-        real tr = real(0);
-        for (int f = 0; f < 9; ++f) {
-          const real x = a.r[((size_t)f * a.K + k) * NP + i] * inv;
-          X[f * NP + i] = x;
-          if (f >= 3 && f < 6) tr += x;
-        }
-        X[9 * NP + i] = tr;
+      for (int f = 0; f < 9; ++f) {
+        const real x = a.r[((size_t)f * a.K + k) * NP + i] * inv;
+        X[f * NP + i] = x;
+        if (f >= 3 && f < 6) tr += x;
       }
+      X[9 * NP + i] = tr;
     }
-    const real* wr = a.rho_inv + (size_t)k * MP;
-    const real* wl = a.lam + (size_t)k * MP;
-    const real* wm = a.mu + (size_t)k * MP;
+    for (int t = lane; t < 3 * MP; t += 64) {
+      const int w = t / MP, b = t - w * MP;
+      const real* src = w == 0 ? a.rho_inv : (w == 1 ? a.lam : a.mu);
+      const uint4 e = itab[b];  // beta at position b (|beta| <= M)
+      const int b1 = (e.z >> 16) & 255, b2 = e.z >> 24, b3 = e.w & 255, sb = e.w >> 8;
+      Wt[t] = src[(size_t)k * MP + b] * real(1.0 / (factd(M - sb) * factd(b1) * factd(b2) * factd(b3)));
+    }
     wsync();
-    for (int c = 0; c < 9; ++c) {
-      // product h = w1 f1 (+ w2 f2) in degree N + M (eq. mcoeff, scaled form)
-      const real* w1 = c < 3 ? wr : (c < 6 ? wl : wm);
-      const int f1 = c < 3 ? c : (c < 6 ? 9 : c);
-      const real s1 = real(1);
-      const real* w2 = c >= 3 && c < 6 ? wm : nullptr;
-      const int f2 = c;
-      const real s2 = real(2);
+    for (int c0 = 0; c0 < 9; c0 += G) {
+      // products (eq. mcoeff, scaled form): velocities rho^{-1} v_i, normal stresses
+      // lambda tr + 2 mu sigma_i, shear stresses mu sigma_s
+      real* const P = M > 0 ? A : LV;  // with M = 0 the product is level 0 itself
+      const int pst = M > 0 ? NH : LEV;
+      for (int t = lane; t < G * NH; t += 64) {
+        const int cl = t / NH, i = t - cl * NH, c = c0 + cl;
+        const int f1 = c < 3 ? c : (c < 6 ? 9 : c);
+        const real* w1 = Wt + (c < 3 ? 0 : (c < 6 ? 1 : 2)) * MP;
+        const bool two = c >= 3 && c < 6;
+        real h = real(0);
 #pragma unroll
-      for (int s = 0; s < SH; ++s) {
-        const int i = lane + 64 * s;
-        if (i < NH) {
-          real h = real(0);
-          int b = 0;
-#pragma unroll
-          for (int sb = 0; sb <= M; ++sb)
-#pragma unroll
-            for (int b3 = 0; b3 <= sb; ++b3)
-#pragma unroll
-              for (int b2 = 0; b2 <= sb - b3; ++b2, ++b) {
-                const int p = ptab[b * NH + i];
-                if (p == 255) continue;
-                const real bf = real(1.0 / (factd(M - sb) * factd(sb - b2 - b3) * factd(b2) * factd(b3)));
-                h += X[f1 * NP + p] * (s1 * w1[b] * bf);
-                if (w2) h += X[f2 * NP + p] * (s2 * w2[b] * bf);
-              }
-          H[i] = h * facH[s];
+        for (int b = 0; b < MP; ++b) {
+          const int p = ptab[b * NH + i];
+          if (p == 255) continue;
+          h += X[f1 * NP + p] * w1[b];
+          if (two) h += real(2) * X[c * NP + p] * Wt[2 * MP + b];
         }
+        P[cl * pst + i] = h * facH[i];
       }
       wsync();
-      // M one-degree reductions N+M -> N: y_a = [(a0+1) x_a + sum_j (a_j + 1) x_{a+e_j}] / n
-      real* src = H;
-      for (int n = N + M; n > N; --n) {
-        real* dst = (n - 1 == N) ? LV : (src == H ? T : H);
-        const int cnt = dimp(n - 1);
+      // M reductions N+M -> N (ping-pong A <-> B, the last into level 0)
+      if constexpr (M > 0) {
+        const real* src = A;
+        int sst = NH;
 #pragma unroll
-        for (int s = 0; s < SH; ++s) {
-          const int i = lane + 64 * s;
-          if (i < cnt) {
-            const int a1 = m1[s], a2 = m2[s], a3 = m3[s], a0 = n - 1 - a1 - a2 - a3;
-            dst[i] = (real(a0 + 1) * src[i] + real(a1 + 1) * src[up1[s]] + real(a2 + 1) * src[up2[s]] +
-                      real(a3 + 1) * src[up3[s]]) / real(n);
-          }
+        for (int n = N + M; n > N; --n) {
+          const bool last = n - 1 == N;
+          real* dst = last ? LV : (src == A ? B : A);
+          const int dstr = last ? LEV : (src == A ? NB : NH);
+          reduce(src, sst, dst, dstr, n);
+          src = dst;
+          sst = dstr;
         }
-        wsync();
-        src = dst;
       }
-      if constexpr (M == 0) {  // no reduction: level 0 is the product itself
+      // downward sweep: level j = reduction of level j - 1
 #pragma unroll
-        for (int s = 0; s < SH; ++s) {
-          const int i = lane + 64 * s;
-          if (i < NP) LV[i] = H[i];
-        }
-        wsync();
-      }
-      // downward sweep: level j = reduction of level j - 1 (degree N - j + 1 -> N - j)
-      for (int j = 1; j <= N; ++j) {
-        const int n = N - j + 1;
-        const real* lsrc = LV + lev_base(N, j - 1);
-        real* ldst = LV + lev_base(N, j);
-        const int cnt = dimp(n - 1);
-#pragma unroll
-        for (int s = 0; s < SH; ++s) {
-          const int i = lane + 64 * s;
-          if (i < cnt) {
-            const int a1 = m1[s], a2 = m2[s], a3 = m3[s], a0 = n - 1 - a1 - a2 - a3;
-            ldst[i] = (real(a0 + 1) * lsrc[i] + real(a1 + 1) * lsrc[up1[s]] + real(a2 + 1) * lsrc[up2[s]] +
-                       real(a3 + 1) * lsrc[up3[s]]) / real(n);
-          }
-        }
-        wsync();
-      }
+      for (int j = 1; j <= N; ++j) reduce(LV + lev_base(N, j - 1), LEV, LV + lev_base(N, j), LEV, N - j + 1);
       // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E s_{j+1}, (E y)_g = sum_{g_j > 0} g_j / n y_{g - e_j}
-      if (lane == 0) LV[lev_base(N, N)] *= a.cj[N];
+      if (lane < G) LV[lane * LEV + lev_base(N, N)] *= a.cj[N];
       wsync();
+#pragma unroll
       for (int j = N - 1; j >= 0; --j) {
-        const int n = N - j;  // degree of level j
-        real* lo = LV + lev_base(N, j);
-        const real* hi = LV + lev_base(N, j + 1);
-        const int cnt = dimp(n);
-        const real cj = a.cj[j];
-        real v[SH];
-#pragma unroll
-        for (int s = 0; s < SH; ++s) {
-          const int i = lane + 64 * s;
-          v[s] = real(0);
-          if (i < cnt) {
-            const int a1 = m1[s], a2 = m2[s], a3 = m3[s], a0 = n - a1 - a2 - a3;
-            real e = real(0);
-            if (a0 > 0) e += real(a0) * hi[i];
-            e += real(a1) * hi[dn1[s]] + real(a2) * hi[dn2[s]] + real(a3) * hi[dn3[s]];  // zero weight where a_j = 0
-            v[s] = cj * lo[i] + e / real(n);
-          }
-        }
-        wsync();  // every lane has read level j before it is overwritten
-#pragma unroll
-        for (int s = 0; s < SH; ++s) {
-          const int i = lane + 64 * s;
-          if (i < cnt) lo[i] = v[s];
+        const int n = N - j, cnt = dimp(n);
+        const real cj = a.cj[j], inv = real(1) / real(n);
+        for (int t = lane; t < G * cnt; t += 64) {
+          const int cl = t / cnt, i = t - cl * cnt;
+          const uint4 e = itab[i];
+          const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - (int)(e.w >> 8);
+          real* lo = LV + cl * LEV + lev_base(N, j);
+          const real* hi = LV + cl * LEV + lev_base(N, j + 1);
+          real el = real(a1) * hi[e.y & 0xFFFF] + real(a2) * hi[e.y >> 16] + real(a3) * hi[e.z & 0xFFFF];
+          if (a0 > 0) el += real(a0) * hi[i];
+          lo[i] = cj * lo[i] + inv * el;  // only this item reads lo[i]
         }
         wsync();
       }
-#pragma unroll
-      for (int s = 0; s < SH; ++s) {
-        const int i = lane + 64 * s;
-        if (s * 64 < NP && i < NP) a.out[((size_t)c * a.K + k) * NP + i] = LV[i];
+      for (int t = lane; t < G * NP; t += 64) {
+        const int cl = t / NP, i = t - cl * NP;
+        a.out[((size_t)(c0 + cl) * a.K + k) * NP + i] = LV[cl * LEV + i];
       }
-      wsync();  // H, T and the levels are reused by the next component
+      wsync();  // the buffers are reused by the next group and element
     }
   }
 }
 
 template <typename real, int N, int M>
 int launch_typed(const ElasticArgs<real>& a, void* stream) {
-  constexpr int WPB = ElasticLayout<N, M>::template waves<real>();
+  constexpr int WPB = ElasticLayout<real, N, M>::WAVES;
   int dev = 0, ncu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int64_t want = (a.K + WPB - 1) / WPB;
   const int64_t cap = (int64_t)(ncu > 0 ? ncu : 256) * 16;
   const int64_t blocks = want < cap ? want : cap;
-  hipLaunchKernelGGL((elastic_update_kernel<real, N, M, WPB>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
+  hipLaunchKernelGGL((elastic_update_kernel<real, N, M>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
                      (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
