@@ -263,18 +263,25 @@ int bbwadg_receiver_elements(const bbwadg_ctx* ctx, int32_t* elem_out);
  * z = (M S)^{-1} lambda (S = diag(1, -1, -1, -1) reflects the velocity, M is the block mass
  * matrix): the DG operator's symmetric part is the penalty alone, which does not couple p and
  * u, so A^T (M S) = (M S) B W with B the plain DG operator and W the weight-adjusted
- * projection, and each transposed stage is two stage-kernel launches. The forward states are
+ * projection, and each transposed stage is one update launch (W, as bbwadg_wadg_update) and
+ * one stage-kernel launch (B). The forward states are
  * checkpointed every checkpoint_every steps and each segment is recomputed once, storing the
  * pressure part of B q for its 5 checkpoint_every stages. Device memory allocated and freed
- * inside the call: about (5 + nsteps/checkpoint_every) states and, with grad,
- * 5 checkpoint_every + 5 more; synchronises `stream`. EINVAL without receivers. */
+ * inside the call: about (3 + nsteps/checkpoint_every) states and, with grad, the pressure
+ * part of 5 checkpoint_every stages and 4 states more; synchronises `stream`. EINVAL without receivers. */
 int bbwadg_misfit_gradient(bbwadg_ctx* ctx, const void* q0, double t0, double dt, int32_t nsteps, const double* data,
                            int32_t checkpoint_every, double* traces, double* misfit, double* grad, void* stream);
 
 /* The transposed operator in the variables of bbwadg_misfit_gradient: out = B(W z), i.e.
  * A^T (M S z) = M S out. For device states z, out [4][K][Np] of the context dtype (no
- * overlap). Allocates two state-sized temporaries; synchronises `stream`. */
+ * overlap). Allocates one state-sized temporary; synchronises `stream`. */
 int bbwadg_adjoint_apply(bbwadg_ctx* ctx, const void* z, void* out, void* stream);
+
+/* The weight-adjusted update on its own (paper Section 5, the update kernel of Table am1):
+ * out = Pi_N(c^2_M r), the product with c^2_M exact in degree N + M (eq. mcoeff) and Pi_N the
+ * telescoped projection (Theorem 5.1). r, out: device [K][Np] of the context dtype, no
+ * overlap. EC2 without c^2. The fused stage kernel computes the same update internally. */
+int bbwadg_wadg_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
 
 /* ---- elastic weight-adjusted update (paper Section 2.2, eq. ewadg) ----------------------
  * The velocity-stress system rho v_t = sum_i A_i^T d sigma/dx_i, C^{-1} sigma_t = sum_i A_i

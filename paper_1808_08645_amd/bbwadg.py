@@ -31,6 +31,7 @@ EXPORTS = (
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
+    "bbwadg_wadg_update",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
     "bbwadg_sur_train_step",
@@ -108,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_adjoint_apply": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_elastic_set_media": (C.c_int, [vp, pd, pd, pd]),
         "bbwadg_elastic_update": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_wadg_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
         "bbwadg_sur_destroy": (C.c_int, [vp]),
         "bbwadg_sur_num_params": (C.c_int64, [vp]),
@@ -348,6 +350,20 @@ class Solver:
         self._check_state(out, "out")
         _check(self._lib.bbwadg_adjoint_apply(self._ctx, C.c_void_p(z.data_ptr()), C.c_void_p(out.data_ptr()),
                                               self._stream()))
+        return out
+
+    def wadg_update(self, r, out=None):
+        """out = Pi_N(c^2_M r) for one field r [K, Np] (device, context dtype)."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        for t, name in ((r, "r"), (out, "out")):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want or
+                                  tuple(t.shape) != (self.K, self.Np) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous device {want} tensor of shape ({self.K}, {self.Np})")
+        if out is None:
+            out = torch.empty_like(r)
+        _check(self._lib.bbwadg_wadg_update(self._ctx, C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            self._stream()))
         return out
 
     # ------------------------------------------------------------------ elastic update

@@ -92,6 +92,10 @@ struct ElasticArgs {
 };
 template <typename real>
 int launch_elastic_update(int N, int M, const ElasticArgs<real>& a, void* stream);
+// The same kernel on one field with one weight (rho_inv holds the weight, r/out [K][Np]):
+// out = Pi_N(w r), the acoustic weight-adjusted update on its own.
+template <typename real>
+int launch_wadg_update(int N, int M, const ElasticArgs<real>& a, void* stream);
 
 // Adjoint helpers (adjoint_kernel.hip); each returns a hipError_t value cast to int.
 // Tables at the dense rule (exact to degree 2N + M), in MFMA operand order as DenseArgs:

@@ -48,43 +48,49 @@ template <typename real, int N, int M>
 constexpr int elastic_tables() {  // product positions (bytes), stencil table (16 B), gamma! kappa
   return dimp(M) * dimp(N + M) + 16 * dimp(N + M) + (int)sizeof(real) * dimp(N + M);
 }
-template <typename real, int N, int M>
+// NC = 9: the elastic update (9 inputs and the trace, 3 media); NC = 1: one field and one
+// weight (the acoustic update Pi_N(c^2_M r)).
+template <typename real, int N, int M, int NC>
 constexpr int elastic_per_wave(int G) {
-  return (10 * dimp(N) + 3 * dimp(M) + G * (dimp(N + M) + dimp(N + M - 1) + lev_base(N, N + 1))) * (int)sizeof(real);
+  constexpr int XF = NC == 9 ? 10 : 1, NW = NC == 9 ? 3 : 1;
+  return (XF * dimp(N) + NW * dimp(M) + G * (dimp(N + M) + dimp(N + M - 1) + lev_base(N, N + 1))) * (int)sizeof(real);
 }
+
 // LDS bytes a wavefront's buffers may take when choosing the group size (occupancy against
 // fewer, wider phases).
 #ifndef BBW_EL_WAVE_BYTES
 #define BBW_EL_WAVE_BYTES 8192
 #endif
 
-template <typename real, int N, int M>
+template <typename real, int N, int M, int NC>
 constexpr int elastic_group() {
   constexpr int T = elastic_tables<real, N, M>();
   auto fits = [](int G) {
-    const int w = elastic_per_wave<real, N, M>(G);
+    const int w = elastic_per_wave<real, N, M, NC>(G);
     return w <= BBW_EL_WAVE_BYTES && w + T <= 61440;
   };
-  return fits(9) ? 9 : (fits(3) ? 3 : 1);
+  return NC == 1 ? 1 : (fits(9) ? 9 : (fits(3) ? 3 : 1));
 }
-template <typename real, int N, int M>
+template <typename real, int N, int M, int NC>
 constexpr int elastic_waves() {
-  constexpr int room = (61440 - elastic_tables<real, N, M>()) / elastic_per_wave<real, N, M>(elastic_group<real, N, M>());
+  constexpr int room =
+      (61440 - elastic_tables<real, N, M>()) / elastic_per_wave<real, N, M, NC>(elastic_group<real, N, M, NC>());
   return room >= 4 ? 4 : (room >= 1 ? room : 1);
 }
 
-template <typename real, int N, int M>
+template <typename real, int N, int M, int NC>
 struct ElasticLayout {
   static constexpr int NP = dimp(N), NH = dimp(N + M), MP = dimp(M), NB = dimp(N + M - 1);
   static constexpr int LEV = lev_base(N, N + 1);  // levels r_0 .. r_N
-  static constexpr int G = elastic_group<real, N, M>(), WAVES = elastic_waves<real, N, M>();
-  static constexpr int OFF_X = 0, OFF_W = 10 * NP, OFF_A = OFF_W + 3 * MP, OFF_B = OFF_A + G * NH,
+  static constexpr int XF = NC == 9 ? 10 : 1, NW = NC == 9 ? 3 : 1;
+  static constexpr int G = elastic_group<real, N, M, NC>(), WAVES = elastic_waves<real, N, M, NC>();
+  static constexpr int OFF_X = 0, OFF_W = XF * NP, OFF_A = OFF_W + NW * MP, OFF_B = OFF_A + G * NH,
                        OFF_L = OFF_B + G * NB, TOTAL = OFF_L + G * LEV;
 };
 
-template <typename real, int N, int M>
-__global__ __launch_bounds__((64 * ElasticLayout<real, N, M>::WAVES)) void elastic_update_kernel(ElasticArgs<real> a) {
-  using L = ElasticLayout<real, N, M>;
+template <typename real, int N, int M, int NC>
+__global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void weighted_projection_kernel(ElasticArgs<real> a) {
+  using L = ElasticLayout<real, N, M, NC>;
   constexpr int NP = L::NP, NH = L::NH, MP = L::MP, NB = L::NB, LEV = L::LEV, G = L::G, WPB = L::WAVES;
   static_assert(NP < 255, "product positions must fit a byte");
   __shared__ real smem[WPB * L::TOTAL];
@@ -162,14 +168,14 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M>::WAVES)) void elast
       const real inv = real(1.0 / (factd(N - sa) * factd(a1) * factd(a2) * factd(a3)));
       real tr = real(0);
 #pragma unroll
-      for (int f = 0; f < 9; ++f) {
+      for (int f = 0; f < NC; ++f) {
         const real x = a.r[((size_t)f * a.K + k) * NP + i] * inv;
         X[f * NP + i] = x;
         if (f >= 3 && f < 6) tr += x;
       }
-      X[9 * NP + i] = tr;
+      if constexpr (NC == 9) X[9 * NP + i] = tr;
     }
-    for (int t = lane; t < 3 * MP; t += 64) {
+    for (int t = lane; t < L::NW * MP; t += 64) {
       const int w = t / MP, b = t - w * MP;
       const real* src = w == 0 ? a.rho_inv : (w == 1 ? a.lam : a.mu);
       const uint4 e = itab[b];  // beta at position b (|beta| <= M)
@@ -177,16 +183,16 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M>::WAVES)) void elast
       Wt[t] = src[(size_t)k * MP + b] * real(1.0 / (factd(M - sb) * factd(b1) * factd(b2) * factd(b3)));
     }
     wsync();
-    for (int c0 = 0; c0 < 9; c0 += G) {
+    for (int c0 = 0; c0 < NC; c0 += G) {
       // products (eq. mcoeff, scaled form): velocities rho^{-1} v_i, normal stresses
       // lambda tr + 2 mu sigma_i, shear stresses mu sigma_s
       real* const P = M > 0 ? A : LV;  // with M = 0 the product is level 0 itself
       const int pst = M > 0 ? NH : LEV;
       for (int t = lane; t < G * NH; t += 64) {
         const int cl = t / NH, i = t - cl * NH, c = c0 + cl;
-        const int f1 = c < 3 ? c : (c < 6 ? 9 : c);
-        const real* w1 = Wt + (c < 3 ? 0 : (c < 6 ? 1 : 2)) * MP;
-        const bool two = c >= 3 && c < 6;
+        const int f1 = NC == 1 ? 0 : (c < 3 ? c : (c < 6 ? 9 : c));
+        const real* w1 = Wt + (NC == 1 ? 0 : (c < 3 ? 0 : (c < 6 ? 1 : 2))) * MP;
+        const bool two = NC == 9 && c >= 3 && c < 6;
         real h = real(0);
 #pragma unroll
         for (int b = 0; b < MP; ++b) {
@@ -243,53 +249,65 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M>::WAVES)) void elast
   }
 }
 
-template <typename real, int N, int M>
+template <typename real, int N, int M, int NC>
 int launch_typed(const ElasticArgs<real>& a, void* stream) {
-  constexpr int WPB = ElasticLayout<real, N, M>::WAVES;
+  constexpr int WPB = ElasticLayout<real, N, M, NC>::WAVES;
   int dev = 0, ncu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int64_t want = (a.K + WPB - 1) / WPB;
   const int64_t cap = (int64_t)(ncu > 0 ? ncu : 256) * 16;
   const int64_t blocks = want < cap ? want : cap;
-  hipLaunchKernelGGL((elastic_update_kernel<real, N, M>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
+  hipLaunchKernelGGL((weighted_projection_kernel<real, N, M, NC>), dim3((unsigned)blocks), dim3(64 * WPB), 0,
                      (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
-template <typename real, int N>
+template <typename real, int N, int NC>
 int launch_n(int M, const ElasticArgs<real>& a, void* stream) {
   switch (M) {
-    case 0: return launch_typed<real, N, 0>(a, stream);
-    case 1: if constexpr (N >= 1) return launch_typed<real, N, 1>(a, stream); break;
-    case 2: if constexpr (N >= 2) return launch_typed<real, N, 2>(a, stream); break;
-    case 3: if constexpr (N >= 3) return launch_typed<real, N, 3>(a, stream); break;
-    case 4: if constexpr (N >= 4) return launch_typed<real, N, 4>(a, stream); break;
+    case 0: return launch_typed<real, N, 0, NC>(a, stream);
+    case 1: if constexpr (N >= 1) return launch_typed<real, N, 1, NC>(a, stream); break;
+    case 2: if constexpr (N >= 2) return launch_typed<real, N, 2, NC>(a, stream); break;
+    case 3: if constexpr (N >= 3) return launch_typed<real, N, 3, NC>(a, stream); break;
+    case 4: if constexpr (N >= 4) return launch_typed<real, N, 4, NC>(a, stream); break;
     default: break;
   }
   return (int)hipErrorInvalidValue;
+}
+
+template <typename real, int NC>
+int launch_nc(int N, int M, const ElasticArgs<real>& a, void* stream) {
+  if (a.K <= 0) return 0;
+  switch (N) {
+    case 1: return launch_n<real, 1, NC>(M, a, stream);
+    case 2: return launch_n<real, 2, NC>(M, a, stream);
+    case 3: return launch_n<real, 3, NC>(M, a, stream);
+    case 4: return launch_n<real, 4, NC>(M, a, stream);
+    case 5: return launch_n<real, 5, NC>(M, a, stream);
+    case 6: return launch_n<real, 6, NC>(M, a, stream);
+    case 7: return launch_n<real, 7, NC>(M, a, stream);
+    case 8: return launch_n<real, 8, NC>(M, a, stream);
+    case 9: return launch_n<real, 9, NC>(M, a, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 template <typename real>
 int launch_elastic_update(int N, int M, const ElasticArgs<real>& a, void* stream) {
-  if (a.K <= 0) return 0;
-  switch (N) {
-    case 1: return launch_n<real, 1>(M, a, stream);
-    case 2: return launch_n<real, 2>(M, a, stream);
-    case 3: return launch_n<real, 3>(M, a, stream);
-    case 4: return launch_n<real, 4>(M, a, stream);
-    case 5: return launch_n<real, 5>(M, a, stream);
-    case 6: return launch_n<real, 6>(M, a, stream);
-    case 7: return launch_n<real, 7>(M, a, stream);
-    case 8: return launch_n<real, 8>(M, a, stream);
-    case 9: return launch_n<real, 9>(M, a, stream);
-    default: return (int)hipErrorInvalidValue;
-  }
+  return launch_nc<real, 9>(N, M, a, stream);
+}
+
+template <typename real>
+int launch_wadg_update(int N, int M, const ElasticArgs<real>& a, void* stream) {
+  return launch_nc<real, 1>(N, M, a, stream);
 }
 
 template int launch_elastic_update<double>(int, int, const ElasticArgs<double>&, void*);
 template int launch_elastic_update<float>(int, int, const ElasticArgs<float>&, void*);
+template int launch_wadg_update<double>(int, int, const ElasticArgs<double>&, void*);
+template int launch_wadg_update<float>(int, int, const ElasticArgs<float>&, void*);
 
 }  // namespace bbw

@@ -1263,6 +1263,19 @@ int adjoint_setup(bbwadg_ctx* c) {
   return 0;
 }
 
+// out = Pi_N(c^2_M x) for one field (the update kernel on its own).
+template <typename real>
+int wadg_apply(bbwadg_ctx* c, const void* x, void* out, hipStream_t s) {
+  ElasticArgs<real> a{};
+  a.r = (const real*)x;
+  a.out = (real*)out;
+  a.rho_inv = (const real*)c->d_c2;
+  a.K = c->K;
+  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  const int e = launch_wadg_update<real>(c->N, c->M, a, s);
+  return e ? fail(BBWADG_EHIP, "update launch: %s", hipGetErrorString((hipError_t)e)) : 0;
+}
+
 template <typename real>
 int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, int32_t nsteps, const double* data,
                           int32_t ckpt, double* traces, double* misfit, double* grad, hipStream_t s) {
@@ -1318,13 +1331,12 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
     return rc;
   // backward in the variables z = (M S)^{-1} lambda: per reversed stage
   //   v = z_r + b_k z_q;  grad += dt dW/dc(y_k, v);  z_q += dt B W v;  z_r = a_k v
-  void *ys, *zq, *v, *w4, *t4, *zero4;
+  void *ys, *zq, *v, *w4, *t4;
   if ((rc = ws.get(&ys, (size_t)C * 5 * n1 * rb)) || (rc = ws.get(&zq, n4 * rb)) || (rc = ws.get(&v, n4 * rb)) ||
-      (rc = ws.get(&w4, n4 * rb)) || (rc = ws.get(&t4, n4 * rb)) || (rc = ws.get(&zero4, n4 * rb)))
+      (rc = ws.get(&w4, n4 * rb)) || (rc = ws.get(&t4, n4 * rb)))
     return rc;
   if ((rc = hip_check(hipMemsetAsync(zq, 0, n4 * rb, s), "memset")) ||
       (rc = hip_check(hipMemsetAsync(v, 0, n4 * rb, s), "memset")) ||
-      (rc = hip_check(hipMemsetAsync(zero4, 0, n4 * rb, s), "memset")) ||
       (rc = hip_check(hipMemsetAsync(grad, 0, (size_t)K * c->Mp * 8, s), "memset")))
     return rc;
   C2GradArgs<real> ga{};
@@ -1367,7 +1379,7 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
         ga.y = (const real*)((char*)ys + ((size_t)(n - na) * 5 + st) * n1 * rb);
         if ((e = launch_c2grad<real>(c->N, ga, s))) return fail(BBWADG_EHIP, "c2 gradient: %s", hipGetErrorString((hipError_t)e));
         // w4 = (W v_p, v_u), t4 = B w4
-        if ((rc = stage_custom<real>(c, c->M, c->d_c2k, v, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s)) ||
+        if ((rc = wadg_apply<real>(c, v, w4, s)) ||
             (rc = hip_check(hipMemcpyAsync((char*)w4 + n1 * rb, (char*)v + n1 * rb, 3 * n1 * rb, hipMemcpyDeviceToDevice, s),
                             "copy u")) ||
             (rc = stage_custom<real>(c, 0, ones, nullptr, 0.0, false, w4, t4, nullptr, 0, 0, 0, s)))
@@ -1463,6 +1475,35 @@ int bbwadg_misfit_gradient(bbwadg_ctx* c, const void* q0, double t0, double dt, 
   return misfit_gradient_typed<float>(c, q0, t0, dt, nsteps, data, checkpoint_every, traces, misfit, grad, s);
 }
 
+int bbwadg_wadg_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!r || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (r == out) return fail(BBWADG_EINVAL, "r and out must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = sync_c2(c, s))) return rc;
+  int e;
+  if (c->dtype == BBWADG_F64) {
+    ElasticArgs<double> a{};
+    a.r = (const double*)r;
+    a.out = (double*)out;
+    a.rho_inv = (const double*)c->d_c2;
+    a.K = c->K;
+    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = c->tables.cj[j];
+    e = launch_wadg_update<double>(c->N, c->M, a, s);
+  } else {
+    ElasticArgs<float> a{};
+    a.r = (const float*)r;
+    a.out = (float*)out;
+    a.rho_inv = (const float*)c->d_c2;
+    a.K = c->K;
+    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (float)c->tables.cj[j];
+    e = launch_wadg_update<float>(c->N, c->M, a, s);
+  }
+  if (e) return fail(BBWADG_EHIP, "update launch: %s", hipGetErrorString((hipError_t)e));
+  return 0;
+}
+
 int bbwadg_elastic_set_media(bbwadg_ctx* c, const double* rho_inv, const double* lam, const double* mu) {
   int rc = require_device(c);
   if (rc) return rc;
@@ -1527,14 +1568,10 @@ int bbwadg_adjoint_apply(bbwadg_ctx* c, const void* z, void* out, void* stream) 
   if ((rc = sync_c2(c, s)) || (rc = adjoint_setup(c))) return rc;
   const size_t n1 = (size_t)c->K * c->Np, n4 = 4 * n1, rb = c->rsz;
   Scratch ws;
-  void *zero4, *w4;
-  if ((rc = ws.get(&zero4, n4 * rb)) || (rc = ws.get(&w4, n4 * rb)) ||
-      (rc = hip_check(hipMemsetAsync(zero4, 0, n4 * rb, s), "memset")))
-    return rc;
-  // w4 = (W z_p, z_u): the weight-adjustment launch writes all four fields (u = 0), so the
-  // velocity is copied in after it
-  rc = c->dtype == BBWADG_F64 ? stage_custom<double>(c, c->M, c->d_c2k, z, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s)
-                              : stage_custom<float>(c, c->M, c->d_c2k, z, 1.0, false, zero4, w4, nullptr, 0, 0, 0, s);
+  void* w4;
+  if ((rc = ws.get(&w4, n4 * rb))) return rc;
+  // w4 = (W z_p, z_u)
+  rc = c->dtype == BBWADG_F64 ? wadg_apply<double>(c, z, w4, s) : wadg_apply<float>(c, z, w4, s);
   if (rc ||
       (rc = hip_check(hipMemcpyAsync((char*)w4 + n1 * rb, (const char*)z + n1 * rb, 3 * n1 * rb, hipMemcpyDeviceToDevice, s),
                       "copy u")))

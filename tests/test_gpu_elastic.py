@@ -89,3 +89,44 @@ def test_elastic_error_paths(bb):
         s.elastic_set_media(bad, bad * 0 + 1, bad * 0 + 1)
     with pytest.raises(ValueError):
         s.elastic_update(torch.zeros((4, s.K, s.Np), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("N,M", [(1, 0), (2, 1), (3, 3), (5, 2), (7, 3), (9, 4)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_wadg_update_matches_oracle(bb, N, M, dtype):
+    """The acoustic update on its own, Pi_N(c^2_M r), against P_q diag(c^2_M) V_q r."""
+    import torch
+    from workloads import random_c2_coefficients
+    print(f"[wadg update] N={N} M={M} {dtype}", flush=True)
+    xyz, etov = kuhn_cube_mesh(2)
+    etov = etov[:29]
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    c2 = random_c2_coefficients(97, s.K, s.Mp)
+    r = np.random.default_rng(98).standard_normal((s.K, s.Np))
+    if dtype == "f32":
+        c2, r = c2.astype(np.float32).astype(np.float64), r.astype(np.float32).astype(np.float64)
+    s.set_c2(c2)
+    out = s.wadg_update(torch.as_tensor(r, device="cuda").to(torch.float64 if dtype == "f64" else torch.float32))
+    o = Oracle(xyz, etov, N, M)
+    o.set_c2_bernstein(c2)
+    Rm = o.from_bernstein(r[None])[0]
+    ref = ((Rm @ o.Vq.T) * o.c2q) @ o.Pq.T
+    err = o.rel_l2(o.bernstein_values_at_quad(out.double().cpu().numpy()[None]), o.values_at_quad(ref[None]))
+    tol = 1e-11 if dtype == "f64" else (1e-5 if N <= 7 else 2e-4)
+    assert np.all(err < tol), err
+
+
+def test_wadg_update_full_size_equals_dense_update(bb):
+    """196,608 tets, N=5, M=2: the Bernstein update and the dense quadrature update with c^2_M at
+    the points compute the same projection."""
+    import torch
+    print("[wadg update full size]", flush=True)
+    xyz, etov = kuhn_cube_mesh(32)
+    s = bb.Solver(xyz, etov, 5, 2)
+    s.project_c2(c2_gaussian_bumps(0))
+    s.dense_set_c2(None)
+    r = torch.as_tensor(np.random.default_rng(99).standard_normal((s.K, s.Np)), device="cuda")
+    a = s.wadg_update(r)
+    b = s.dense_update(r)
+    rel = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    assert rel < 1e-12, rel
