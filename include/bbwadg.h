@@ -265,8 +265,9 @@ int bbwadg_receiver_elements(const bbwadg_ctx* ctx, int32_t* elem_out);
  * u, so A^T (M S) = (M S) B W with B the plain DG operator and W the weight-adjusted
  * projection, and each transposed stage is one update launch (W, as bbwadg_wadg_update) and
  * one stage-kernel launch (B). The forward states are
- * checkpointed every checkpoint_every steps and each segment is recomputed once, storing the
- * pressure part of B q for its 5 checkpoint_every stages. Device memory allocated and freed
+ * checkpointed every checkpoint_every steps and each segment is recomputed once; its update
+ * launches also store the pressure part of B q (r_p before the weight adjustment) of its
+ * 5 checkpoint_every stages. Device memory allocated and freed
  * inside the call: about (3 + nsteps/checkpoint_every) states and, with grad, the pressure
  * part of 5 checkpoint_every stages and 4 states more; synchronises `stream`. EINVAL without receivers. */
 int bbwadg_misfit_gradient(bbwadg_ctx* ctx, const void* q0, double t0, double dt, int32_t nsteps, const double* data,

@@ -33,6 +33,7 @@ struct StageArgs {
   real rk_a, rk_b, dt;    // stage coefficients (step mode)
   const real* src;        // [K][Np] pressure source g (coefficients), or null
   real src_amp;           // s(t) of the source f = s(t) g(x) at this stage's time
+  real* rp_out;           // [K][Np] r_p before the weight adjustment (source included), or null (step mode)
   real cj[kMaxN + 1];     // telescoped projection coefficients c_j
 };
 

@@ -427,6 +427,7 @@ StageArgs<real> make_args(const bbwadg_ctx* c) {
   for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
   a.src = (const real*)c->d_src;
   a.src_amp = real(0);
+  a.rp_out = nullptr;
   return a;
 }
 
@@ -452,11 +453,12 @@ const double kRkB[5] = {1432997174477.0 / 9575080441755.0,
                         2277821191437.0 / 14882151754819.0};
 
 int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, double ra, double rb,
-           double dt, double t, hipStream_t s) {
+           double dt, double t, hipStream_t s, void* rp_out = nullptr) {
   int e;
   const double sf = source_factor(c, t);
   if (c->dtype == BBWADG_F64) {
     StageArgs<double> a = make_args<double>(c);
+    a.rp_out = (double*)rp_out;
     a.src_amp = sf;
     a.qin = (const double*)qin;
     a.qout = (double*)qout;
@@ -467,6 +469,7 @@ int launch(bbwadg_ctx* c, bool update, const void* qin, void* qout, void* res, d
     e = launch_stage_f64(c->N, c->M, update, a, s);
   } else {
     StageArgs<float> a = make_args<float>(c);
+    a.rp_out = (float*)rp_out;
     a.src_amp = (float)sf;
     a.qin = (const float*)qin;
     a.qout = (float*)qout;
@@ -1353,7 +1356,8 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
   int e;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int32_t na = seg * C, nb = std::min(nsteps, na + C);
-    // recompute the segment, keeping y = (B q)_p of every stage input (source included)
+    // recompute the segment, keeping y = (B q)_p of every stage input (source included): the
+    // update launches write it through StageArgs::rp_out
     if ((rc = hip_check(hipMemcpyAsync(qa, (char*)ck + (size_t)seg * n4 * rb, n4 * rb, hipMemcpyDeviceToDevice, s),
                         "restore")))
       return rc;
@@ -1362,11 +1366,9 @@ int misfit_gradient_typed(bbwadg_ctx* c, const void* q0, double t0, double dt, i
     for (int32_t n = na; n < nb; ++n)
       for (int st = 0; st < 5; ++st) {
         const double ts = t0 + (n + kRkC[st]) * dt;
+        // the update launch also writes y = (B q)_p of its input (source included) to the slot
         void* yslot = (char*)ys + ((size_t)(n - na) * 5 + st) * n1 * rb;
-        if ((rc = stage_custom<real>(c, 0, ones, c->d_src, source_factor(c, ts), false, cur, t4, nullptr, 0, 0, 0, s)) ||
-            (rc = hip_check(hipMemcpyAsync(yslot, t4, n1 * rb, hipMemcpyDeviceToDevice, s), "copy y")) ||
-            (rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, ts, s)))
-          return rc;
+        if ((rc = launch(c, true, cur, nxt, res, kRkA[st], kRkB[st], dt, ts, s, yslot))) return rc;
         std::swap(cur, nxt);
       }
     for (int32_t n = nb - 1; n >= na; --n) {

@@ -213,7 +213,7 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 #define BBW_WAVES_EU 0
 #endif
 
-template <typename real, int N, int M, int EW, int WPB, bool UPDATE>
+template <typename real, int N, int M, int EW, int WPB, bool UPDATE, bool RPOUT = false>
 __global__ __launch_bounds__(64 * WPB)
 #if BBW_WAVES_EU > 0
 __attribute__((amdgpu_waves_per_eu(BBW_WAVES_EU < StageLayout<real, N, M, EW>::WAVES_EU ? BBW_WAVES_EU : StageLayout<real, N, M, EW>::WAVES_EU, 8)))
@@ -722,6 +722,8 @@ void stage_kernel(const StageArgs<real> a) {
           acc[2][s] += geo_at(e, 11 + 4 * f) * luv;
           acc[3][s] += geo_at(e, 12 + 4 * f) * luv;
         }
+        if constexpr (RPOUT)  // r_p before the weight adjustment (a separate instance, step mode)
+          if (k0 + e < K) a.rp_out[(size_t)(k0 + e) * NP + item / EW] = acc[0][s];
         if constexpr (M > 0) {
           at(wb + BR + item * SZ) = acc[0][s] * fac3[s];
           if constexpr (!L::MUL_REGS)
@@ -886,12 +888,12 @@ void stage_kernel(const StageArgs<real> a) {
   }
 }
 
-template <typename real, int N, int M, bool UPDATE>
+template <typename real, int N, int M, bool UPDATE, bool RPOUT = false>
 int launch_stage_typed(const StageArgs<real>& a, void* stream) {
   constexpr int EW = elems_per_wave<N>();
   using L = StageLayout<real, N, M, EW>;
   constexpr int WPB = L::WPB;
-  auto kern = stage_kernel<real, N, M, EW, WPB, UPDATE>;
+  auto kern = stage_kernel<real, N, M, EW, WPB, UPDATE, RPOUT>;
   // persistent grid: the blocks resident on the current device, a multiple of 8; computed
   // once per device (benign if two threads compute it concurrently: same value)
   constexpr int kMaxDevices = 64;
@@ -979,10 +981,12 @@ template <int N, int M>
 int dispatch_nm(bool update, bool f64, const void* args, void* stream) {
   if (f64) {
     const auto& a = *static_cast<const StageArgs<double>*>(args);
-    return update ? launch_stage_typed<double, N, M, true>(a, stream) : launch_stage_typed<double, N, M, false>(a, stream);
+    if (!update) return launch_stage_typed<double, N, M, false>(a, stream);
+    return a.rp_out ? launch_stage_typed<double, N, M, true, true>(a, stream) : launch_stage_typed<double, N, M, true>(a, stream);
   }
   const auto& a = *static_cast<const StageArgs<float>*>(args);
-  return update ? launch_stage_typed<float, N, M, true>(a, stream) : launch_stage_typed<float, N, M, false>(a, stream);
+  if (!update) return launch_stage_typed<float, N, M, false>(a, stream);
+  return a.rp_out ? launch_stage_typed<float, N, M, true, true>(a, stream) : launch_stage_typed<float, N, M, true>(a, stream);
 }
 
 // All c^2 degrees M <= min(N, kMaxM) of one polynomial degree N.
