@@ -175,7 +175,7 @@ def c3_sweep(steps, warmup):
     return out
 
 
-def wadg_compare(n_list, m_list, reps):
+def wadg_compare(n_list, m_list, reps, cells=None):
     """Dense quadrature WADG (matrix cores) against the Bernstein update on the 196,608-tet mesh:
     times of the fused Bernstein right-hand side, the plain DG right-hand side (c^2 = 1, no
     weight adjustment), and the dense update alone, with c^2_M of the bump medium at the points."""
@@ -183,7 +183,7 @@ def wadg_compare(n_list, m_list, reps):
 
     import paper_1808_08645_amd as bb
     from workloads import kuhn_cube_mesh
-    xyz, etov = kuhn_cube_mesh(CELLS)
+    xyz, etov = kuhn_cube_mesh(cells or CELLS)
 
     def timed(fn):
         fn()
@@ -222,6 +222,9 @@ def wadg_compare(n_list, m_list, reps):
             e = {"N": n, "M": m, "Np": s.Np, "nq_dense": s.dense_npoints(), "rhs_bernstein_ms": t_bb,
                  "rhs_dense_ms": t_dense_rhs, "dense_update_ms": t_dense, "plain_dg_rhs_ms": t_dg,
                  "bernstein_update_ms": t_bupd, "fused_minus_plain_ms": t_bb - t_dg,
+                 "elements": s.K, "bernstein_update_us_per_element": t_bupd * 1e3 / s.K,
+                 "dense_update_us_per_element": t_dense * 1e3 / s.K,
+                 "bernstein_update_gb_s": (2 * s.Np + s.Mp) * 8 * s.K / (t_bupd * 1e-3) / 1e9,
                  "dense_update_tflops": 4.0 * s.dense_npoints() * s.Np * s.K / (t_dense * 1e-3) / 1e12}
             out.append(e)
             print(json.dumps({"wadg_compare_progress": e}), file=sys.stderr, flush=True)
@@ -503,6 +506,7 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="instead of the default workload: misfit gradient on 82,944 tets, N=4, M=2, 500 steps")
     ap.add_argument("--adjoint-steps", type=int, default=500)
+    ap.add_argument("--wadg-compare-cells", type=int, default=32, help="cube cells per side for --wadg-compare")
     ap.add_argument("--surrogate", action="store_true",
                     help="instead of the default workload: train and judge the trace surrogate (256 media)")
     ap.add_argument("--surrogate-media", type=int, default=256)
@@ -522,8 +526,10 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     if args.wadg_compare:
-        res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps))
-        print(json.dumps({"workload": "cube196k, bump medium, c^2_M at the dense points", "unit": "ms per evaluation",
+        res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps), args.wadg_compare_cells)
+        k = 6 * args.wadg_compare_cells ** 3
+        print(json.dumps({"workload": f"cube {args.wadg_compare_cells}^3x6 = {k} tets, bump medium, c^2_M at the dense points",
+                          "unit": "ms per evaluation",
                           "reps": max(1, args.steps), "wadg_compare": res}), flush=True)
         return
     if args.elastic:
