@@ -38,3 +38,59 @@ def elastic_update(o: Oracle, R, rho_inv, lam, mu):
         out[3 + i] = wl * tr + 2.0 * wm * V[3 + i]
         out[6 + i] = wm * V[6 + i]
     return out @ o.Pq.T
+
+
+# The matrices A_i of the velocity-stress system (paper Section 2.2, eq. ewave), stress in the
+# Voigt order xx, yy, zz, yz, xz, xy.
+A_MATS = np.zeros((3, 6, 3))
+A_MATS[0, 0, 0] = A_MATS[0, 4, 2] = A_MATS[0, 5, 1] = 1.0
+A_MATS[1, 1, 1] = A_MATS[1, 3, 2] = A_MATS[1, 5, 0] = 1.0
+A_MATS[2, 2, 2] = A_MATS[2, 3, 1] = A_MATS[2, 4, 0] = 1.0
+
+
+def elastic_rhs(o: Oracle, Q, media=None, tau_v: float = 1.0, tau_s: float = 1.0, wall: str = "free"):
+    """DG right-hand side of the velocity-stress system for the state Q [9, K, Np] (modal):
+
+        r_v = sum_i A_i^T d sigma/dx_i + sum_f (J_f/J) L^f F_v,  F_v = A_n^T [[sigma]]/2 + tau_v A_n^T A_n [[v]]/2
+        r_s = sum_i A_i  d v/dx_i      + sum_f (J_f/J) L^f F_s,  F_s = A_n [[v]]/2 + tau_s A_n A_n^T [[sigma]]/2
+
+    with A_n = sum_i n_i A_i (the semi-discrete form after eq. ewave). Walls take mirror states:
+    traction-free ("free") sigma+ = -sigma, v+ = v; rigid v+ = -v, sigma+ = sigma. With
+    ``media`` = (1/rho, lambda, mu) Bernstein coefficients the weight-adjusted update follows
+    (eq. ewadg); without, the pre-update right-hand side is returned."""
+    Q = np.asarray(Q, dtype=np.float64)
+    msh = o.mesh
+    G = msh.G
+    dQ = [Q @ Dj.T for Dj in o.D]
+    dx = [sum(G[:, i, j][None, :, None] * dQ[j] for j in range(3)) for i in range(3)]  # d/dx_i, [9, K, Np]
+    rv = np.zeros_like(Q[:3])
+    rs = np.zeros_like(Q[3:])
+    for i in range(3):
+        rv += np.einsum("ba,bkn->akn", A_MATS[i], dx[i][3:])
+        rs += np.einsum("ba,akn->bkn", A_MATS[i], dx[i][:3])
+    for f in range(4):
+        own = Q @ o.Vf[f].T
+        nb = np.empty_like(own)
+        for sel, ks2, Vn in o.groups[f]:
+            nb[:, sel] = Q[:, ks2] @ Vn.T
+        bm = o.bmask[f]
+        if np.any(bm):
+            if wall == "free":
+                nb[:3, bm] = own[:3, bm]
+                nb[3:, bm] = -own[3:, bm]
+            else:
+                nb[:3, bm] = -own[:3, bm]
+                nb[3:, bm] = own[3:, bm]
+        An = np.einsum("ki,ibc->kbc", msh.normal[:, f], A_MATS)  # [K, 6, 3]
+        jv, js = nb[:3] - own[:3], nb[3:] - own[3:]
+        AnT_js = np.einsum("kba,bkq->akq", An, js)
+        An_jv = np.einsum("kba,akq->bkq", An, jv)
+        Fv = 0.5 * AnT_js + 0.5 * tau_v * np.einsum("kba,bkq->akq", An, An_jv)
+        Fs = 0.5 * An_jv + 0.5 * tau_s * np.einsum("kba,akq->bkq", An, AnT_js)
+        sc = msh.Fscale[:, f][:, None]
+        rv += sc * (Fv @ o.Lf[f].T)
+        rs += sc * (Fs @ o.Lf[f].T)
+    R = np.concatenate([rv, rs])
+    if media is None:
+        return R
+    return elastic_update(o, R, *media)

@@ -59,3 +59,49 @@ def test_matrix_weighted_projection_is_symmetric():
     assert abs(a - b) < 1e-12 * (abs(a) + 1.0)
     # and positive for positive media (lambda, mu > 0): (W r, r) > 0
     assert np.sum(elastic_update(o, R1, rho_inv, lam, mu) * R1) > 0
+
+
+def test_elastic_rhs_conserves_energy_with_central_fluxes():
+    """With tau = 0 and either wall type, sum_k (Q, r(Q))_{L^2} = 0: the volume terms and the
+    central fluxes form a skew operator (a wrong sign or a transposed A_i breaks this)."""
+    from oracle.elastic import elastic_rhs
+    xyz, etov = kuhn_cube_mesh(2)
+    o = Oracle(xyz, etov, 3, 0)
+    Q = np.random.default_rng(7).standard_normal((9, o.mesh.K, o.Np))
+    J = o.mesh.J[None, :, None]
+    for wall in ("free", "rigid"):
+        R = elastic_rhs(o, Q, tau_v=0.0, tau_s=0.0, wall=wall)
+        e = np.sum(J * Q * R)
+        assert abs(e) < 1e-11 * np.sum(J * np.abs(Q) * np.abs(R)), (wall, e)
+        R = elastic_rhs(o, Q, tau_v=1.0, tau_s=0.7, wall=wall)
+        assert np.sum(J * Q * R) < 0  # the penalty terms dissipate
+
+
+def test_elastic_rhs_of_a_global_polynomial_on_interior_elements():
+    """On elements away from the walls the traces agree, so r is the exact derivative term:
+    r_v = div sigma and r_s = the symmetric gradient of v (Voigt, shear entries doubled)."""
+    from oracle.elastic import elastic_rhs
+    xyz, etov = kuhn_cube_mesh(3)
+    o = Oracle(xyz, etov, 3, 0)
+    v = [lambda x, y, z: x * y + z, lambda x, y, z: z * z - x, lambda x, y, z: x * y * z]
+    s = [lambda x, y, z: x * x, lambda x, y, z: y * z, lambda x, y, z: x - y * y * z,
+         lambda x, y, z: x * z, lambda x, y, z: y + z * x * x, lambda x, y, z: x * y]
+    Q = np.stack([o.project_modal(f, o.N) for f in v + s])
+    R = elastic_rhs(o, Q, tau_v=1.0, tau_s=1.0)
+    inner = np.all(o.mesh.nbr >= 0, axis=1)
+    X = o.mesh.map_points(o.rq, o.sq, o.tq)
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    # sxx = x^2, syy = yz, szz = x - y^2 z, syz = xz, sxz = y + z x^2, sxy = xy
+    want = np.stack([
+        2 * x + x + x * x,       # d sxx/dx + d sxy/dy + d sxz/dz
+        y + z + x,               # d sxy/dx + d syy/dy + d syz/dz
+        2 * x * z - y * y,       # d sxz/dx + d syz/dy + d szz/dz
+        y,                       # d v1/dx
+        0 * x,                   # d v2/dy
+        x * y,                   # d v3/dz
+        x * z + 2 * z,           # d v3/dy + d v2/dz
+        y * z + 1.0,             # d v3/dx + d v1/dz
+        x - 1.0,                 # d v2/dx + d v1/dy
+    ])
+    got = o.values_at_quad(R)
+    assert np.max(np.abs(got[:, inner] - want[:, inner])) < 1e-10
