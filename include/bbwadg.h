@@ -303,6 +303,20 @@ int bbwadg_elastic_set_media(bbwadg_ctx* ctx, const double* rho_inv, const doubl
  * bbwadg_elastic_set_media. */
 int bbwadg_elastic_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
 
+/* The elastic DG right-hand side (paper Section 2.2, the semi-discrete form after eq. ewave)
+ * with upwind-type penalty fluxes, A_n = sum_i n_i A_i on each face:
+ *   r_v = sum_i A_i^T d sigma/dx_i + sum_f (J_f/J) L^f F_v,  F_v = A_n^T [[sigma]]/2 + tau_v/2 A_n^T A_n [[v]]
+ *   r_s = sum_i A_i   d v/dx_i     + sum_f (J_f/J) L^f F_s,  F_s = A_n [[v]]/2     + tau_s/2 A_n A_n^T [[sigma]]
+ * ([[u]] = u+ - u-, L^f the lift of face f). Boundary faces take the mirror state of `wall`:
+ * 0 traction-free (sigma+ = -sigma, v+ = v), 1 rigid (v+ = -v, sigma+ = sigma). q, rhs: device
+ * [9][K][Np] of the context dtype, no overlap. weighted = 0 returns the right-hand side before
+ * the media enter; weighted = 1 follows it with bbwadg_elastic_update (EC2 before
+ * bbwadg_elastic_set_media) through a context-owned [9][K][Np] temporary, allocated on the first
+ * such call. EINVAL for a bad wall or a negative or non-finite tau. The lift tables are built on
+ * the first call. */
+int bbwadg_elastic_rhs(bbwadg_ctx* ctx, const void* q, void* rhs, int32_t wall, double tau_v, double tau_s,
+                       int32_t weighted, void* stream);
+
 /* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
  * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
  * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */

@@ -31,6 +31,7 @@ EXPORTS = (
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
+    "bbwadg_elastic_rhs",
     "bbwadg_wadg_update",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_adjoint_apply": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_elastic_set_media": (C.c_int, [vp, pd, pd, pd]),
         "bbwadg_elastic_update": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_elastic_rhs": (C.c_int, [vp, vp, vp, i32, dbl, dbl, i32, vp]),
         "bbwadg_wadg_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
         "bbwadg_sur_destroy": (C.c_int, [vp]),
@@ -391,6 +393,25 @@ class Solver:
             out = torch.empty_like(r)
         _check(self._lib.bbwadg_elastic_update(self._ctx, C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
                                                self._stream()))
+        return out
+
+    def elastic_rhs(self, q, out=None, wall: str = "free", tau_v: float = 1.0, tau_s: float = 1.0,
+                    weighted: bool = True):
+        """Elastic DG right-hand side of q [9, K, Np] (device); weighted=True applies the
+        weight-adjusted update of the media set by elastic_set_media."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        for t, name in ((q, "q"), (out, "out")):
+            if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want or
+                                  tuple(t.shape) != (9, self.K, self.Np) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous device {want} tensor of shape (9, {self.K}, {self.Np})")
+        if wall not in ("free", "rigid"):
+            raise ValueError("wall must be 'free' or 'rigid'")
+        if out is None:
+            out = torch.empty_like(q)
+        _check(self._lib.bbwadg_elastic_rhs(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()),
+                                            0 if wall == "free" else 1, float(tau_v), float(tau_s),
+                                            1 if weighted else 0, self._stream()))
         return out
 
     def suggest_dt(self, cfl: float) -> float:

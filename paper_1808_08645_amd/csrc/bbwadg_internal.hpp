@@ -98,6 +98,23 @@ int launch_elastic_update(int N, int M, const ElasticArgs<real>& a, void* stream
 template <typename real>
 int launch_wadg_update(int N, int M, const ElasticArgs<real>& a, void* stream);
 
+// DG right-hand side of the elastic system before the weight adjustment
+// (elastic_rhs_kernel.hip): q, out [9][K][Np].
+template <typename real>
+struct ElasticRhsArgs {
+  const real* q;
+  real* out;
+  const real* geo;       // [K][kGeoStride]
+  const int32_t* conn;   // [K][4]
+  const int32_t* fpos;   // [4][Nfp] volume position of face coefficient m of face f
+  const real* lift;      // [4][Np][Nfp] L^f = M^{-1} M_f in the Bernstein basis (reference face area 2)
+  int64_t K;
+  real tau_v, tau_s;
+  int32_t wall;          // 0: traction-free, 1: rigid
+};
+template <typename real>
+int launch_elastic_rhs(int N, const ElasticRhsArgs<real>& a, void* stream);
+
 // Adjoint helpers (adjoint_kernel.hip); each returns a hipError_t value cast to int.
 // Tables at the dense rule (exact to degree 2N + M), in MFMA operand order as DenseArgs:
 // va = V_q (NQP/16 x NPP/4 x 64) and bwa[qc][ks][lane] = w_q B^M_g(x_q) for
