@@ -434,7 +434,8 @@ def elastic_bench(reps=20, only=None):
     """Elastic weight-adjusted update (9 fields, isotropic media projected to P^M), N = 2..9,
     M = 1, 2, on the 11^3 x 6 = 7,986-tet mesh (about the size of the paper's 7,854-element timing
     mesh) and on the 196,608-tet mesh: time per launch and per element, FP64 and FP32, next to
-    nine dense quadrature updates (the cost of the same update by quadrature WADG)."""
+    nine dense quadrature updates (the cost of the same update by quadrature WADG); and the
+    elastic DG right-hand side, with and without the update, and one 5-stage time step."""
     import torch
 
     import paper_1808_08645_amd as bb
@@ -468,6 +469,15 @@ def elastic_bench(reps=20, only=None):
                     o = torch.empty_like(r)
                     ms = timed(lambda: s.elastic_update(r, o))
                     e[dtype] = {"ms": ms, "us_per_element": ms * 1e3 / s.K}
+                    # the DG right-hand side before the media: reads the 9 fields and the 9
+                    # neighbour face traces, writes 9 fields (algorithmic bytes per element)
+                    rb = r.element_size() * (9 * s.Np * 2 + 9 * 4 * s.Nfp + 25) + 16
+                    rms = timed(lambda: s.elastic_rhs(r, o, wall="free", weighted=False))
+                    e[dtype]["rhs_ms"] = rms
+                    e[dtype]["rhs_GBps"] = rb * s.K / (rms * 1e-3) / 1e9
+                    e[dtype]["rhs_weighted_ms"] = timed(lambda: s.elastic_rhs(r, o, wall="free", weighted=True))
+                    res = torch.zeros_like(r)
+                    e[dtype]["step_ms"] = timed(lambda: s.elastic_step(r, res, 1e-9, 1, wall="free"))
                     if dtype == "f64":
                         s.project_c2(c2_gaussian_bumps(0))
                         s.dense_set_c2(None)
@@ -535,7 +545,7 @@ def main():
     if args.elastic:
         only = tuple(int(v) for v in args.elastic_only.split(",")) if args.elastic_only else None
         res = elastic_bench(max(1, min(args.steps, 50)), only)
-        print(json.dumps({"workload": "elastic update: cubes 11^3x6 and 32^3x6, N=2..9, M=1,2", "unit": "ms per update",
+        print(json.dumps({"workload": "elastic update, right-hand side and step: cubes 11^3x6 and 32^3x6, N=2..9, M=1,2", "unit": "ms per call",
                           "data": "synthetic", "elastic": res}), flush=True)
         return
     if args.surrogate:

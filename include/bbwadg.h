@@ -317,6 +317,14 @@ int bbwadg_elastic_update(bbwadg_ctx* ctx, const void* r, void* out, void* strea
 int bbwadg_elastic_rhs(bbwadg_ctx* ctx, const void* q, void* rhs, int32_t wall, double tau_v, double tau_s,
                        int32_t weighted, void* stream);
 
+/* nsteps low-storage RK4 steps (the 5-stage 2N-storage scheme of Carpenter and Kennedy that the
+ * acoustic step uses) of the elastic system: per stage res = a_k res + dt r(q), q += b_k res with
+ * r the weighted right-hand side of bbwadg_elastic_rhs (wall, tau_v, tau_s as there). q, res:
+ * device [9][K][Np] of the context dtype, updated in place, no overlap; res starts at zero for a
+ * fresh run. EC2 before bbwadg_elastic_set_media; EINVAL for dt <= 0, nsteps < 0. */
+int bbwadg_elastic_step(bbwadg_ctx* ctx, void* q, void* res, double dt, int32_t nsteps, int32_t wall, double tau_v,
+                        double tau_s, void* stream);
+
 /* Position of the Bernstein coefficient with multi-index (n - a1 - a2 - a3, a1, a2, a3) in the
  * coefficient order documented above; it does not depend on the degree n >= a1 + a2 + a3
  * (paper Section 2 defines the multi-indices). EINVAL for a negative entry or a1+a2+a3 > 13. */

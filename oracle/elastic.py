@@ -94,3 +94,18 @@ def elastic_rhs(o: Oracle, Q, media=None, tau_v: float = 1.0, tau_s: float = 1.0
     if media is None:
         return R
     return elastic_update(o, R, *media)
+
+
+def elastic_step(o: Oracle, Q, res, dt: float, nsteps: int, media, tau_v: float = 1.0, tau_s: float = 1.0,
+                 wall: str = "free"):
+    """nsteps of the 5-stage low-storage RK4 (the acoustic step's scheme) applied to the
+    weighted elastic right-hand side: per stage res = a_k res + dt r(Q), Q = Q + b_k res.
+    Q, res modal [9, K, Np]."""
+    from .wadg import LSRK4_A, LSRK4_B
+    Q = np.array(Q, dtype=np.float64)
+    res = np.array(res, dtype=np.float64)
+    for _ in range(nsteps):
+        for a, b in zip(LSRK4_A, LSRK4_B):
+            res = a * res + dt * elastic_rhs(o, Q, media, tau_v=tau_v, tau_s=tau_s, wall=wall)
+            Q = Q + b * res
+    return Q, res

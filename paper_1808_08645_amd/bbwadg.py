@@ -31,7 +31,7 @@ EXPORTS = (
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
-    "bbwadg_elastic_rhs",
+    "bbwadg_elastic_rhs", "bbwadg_elastic_step",
     "bbwadg_wadg_update",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_elastic_set_media": (C.c_int, [vp, pd, pd, pd]),
         "bbwadg_elastic_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_elastic_rhs": (C.c_int, [vp, vp, vp, i32, dbl, dbl, i32, vp]),
+        "bbwadg_elastic_step": (C.c_int, [vp, vp, vp, dbl, i32, i32, dbl, dbl, vp]),
         "bbwadg_wadg_update": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
         "bbwadg_sur_destroy": (C.c_int, [vp]),
@@ -413,6 +414,23 @@ class Solver:
                                             0 if wall == "free" else 1, float(tau_v), float(tau_s),
                                             1 if weighted else 0, self._stream()))
         return out
+
+    def elastic_step(self, q, res, dt: float, nsteps: int, wall: str = "free", tau_v: float = 1.0,
+                     tau_s: float = 1.0):
+        """Advance the elastic state q [9, K, Np] (device, in place) by nsteps low-storage RK4
+        steps; res is the 2N-storage register (zero for a fresh run)."""
+        import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
+        for t, name in ((q, "q"), (res, "res")):
+            if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != want or
+                    tuple(t.shape) != (9, self.K, self.Np) or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous device {want} tensor of shape (9, {self.K}, {self.Np})")
+        if wall not in ("free", "rigid"):
+            raise ValueError("wall must be 'free' or 'rigid'")
+        _check(self._lib.bbwadg_elastic_step(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(res.data_ptr()),
+                                             float(dt), int(nsteps), 0 if wall == "free" else 1, float(tau_v),
+                                             float(tau_s), self._stream()))
+        return q, res
 
     def suggest_dt(self, cfl: float) -> float:
         dt = C.c_double()

@@ -320,6 +320,7 @@ struct bbwadg_ctx {
   void* d_el_lift = nullptr;    // [4][Np][Nfp] Bernstein lift (dtype)
   void* d_el_fpos = nullptr;    // [4][Nfp] int32
   void* d_el_tmp = nullptr;     // [9][K][Np] pre-update right-hand side (dtype)
+  void* d_el_rhs = nullptr;     // [9][K][Np] weighted right-hand side of a time step (dtype)
 };
 
 namespace {
@@ -351,7 +352,7 @@ void free_device(bbwadg_ctx* c) {
                    &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
                    &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_bwa,
                    &c->d_adj_ones, &c->d_el_rho, &c->d_el_lam, &c->d_el_mu, &c->d_el_lift,
-                   &c->d_el_fpos, &c->d_el_tmp};
+                   &c->d_el_fpos, &c->d_el_tmp, &c->d_el_rhs};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -1579,6 +1580,33 @@ int bbwadg_elastic_rhs(bbwadg_ctx* c, const void* q, void* rhs, int32_t wall, do
                               : elastic_rhs_typed<float>(c, q, dst, wall, tau_v, tau_s, s);
   if (rc || !weighted) return rc;
   return bbwadg_elastic_update(c, dst, rhs, stream);
+}
+
+int bbwadg_elastic_step(bbwadg_ctx* c, void* q, void* res, double dt, int32_t nsteps, int32_t wall, double tau_v,
+                        double tau_s, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !res) return fail(BBWADG_EINVAL, "NULL state pointer");
+  if (q == res) return fail(BBWADG_EINVAL, "q and res must not overlap");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(BBWADG_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(BBWADG_EINVAL, "nsteps must be >= 0");
+  if (!c->d_el_rho) return fail(BBWADG_EC2, "elastic media not set (call bbwadg_elastic_set_media)");
+  const int64_t n = (int64_t)9 * c->K * c->Np;
+  if (!c->d_el_rhs && (rc = dmalloc(&c->d_el_rhs, (size_t)n * c->rsz))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t it = 0; it < nsteps; ++it)
+    for (int st = 0; st < 5; ++st) {
+      // res = a_k res + dt R(q); q = q + b_k res
+      if ((rc = bbwadg_elastic_rhs(c, q, c->d_el_rhs, wall, tau_v, tau_s, 1, stream))) return rc;
+      int e = c->dtype == BBWADG_F64
+                  ? launch_lincomb<double>((double*)res, (const double*)c->d_el_rhs, kRkA[st], dt, n, s)
+                  : launch_lincomb<float>((float*)res, (const float*)c->d_el_rhs, kRkA[st], dt, n, s);
+      if (!e)
+        e = c->dtype == BBWADG_F64 ? launch_lincomb<double>((double*)q, (const double*)res, 1.0, kRkB[st], n, s)
+                                   : launch_lincomb<float>((float*)q, (const float*)res, 1.0, kRkB[st], n, s);
+      if (e) return fail(BBWADG_EHIP, "elastic step update: %s", hipGetErrorString((hipError_t)e));
+    }
+  return 0;
 }
 
 int bbwadg_wadg_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {

@@ -111,3 +111,33 @@ def test_elastic_rhs_errors(bb):
     with pytest.raises(ValueError):
         s.elastic_rhs(q[:4])
     assert torch.count_nonzero(s.elastic_rhs(q, weighted=False)) == 0
+
+
+@pytest.mark.parametrize("N,M", [(1, 0), (3, 2), (5, 2), (7, 3), (9, 4)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_elastic_step_matches_oracle(bb, N, M, dtype):
+    """Three low-storage RK4 steps of the weighted elastic system (rigid walls) against the
+    oracle's, from a smooth state projected in FP64."""
+    import torch
+    from oracle.elastic import elastic_step
+    print(f"[elastic step] N={N} M={M} {dtype}", flush=True)
+    xyz, etov = _mesh(2, 37, 8)
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    K, Np, Mp = s.K, s.Np, s.Mp
+    media = _media(K, Mp, 140 + M)
+    q = np.random.default_rng(141 + N).standard_normal((9, K, Np)) / N
+    if dtype == "f32":
+        q = q.astype(np.float32).astype(np.float64)
+        media = tuple(x.astype(np.float32).astype(np.float64) for x in media)
+    s.elastic_set_media(*media)
+    dt = 0.02 / (N + 1) ** 2
+    td = torch.float64 if dtype == "f64" else torch.float32
+    qd = torch.as_tensor(q, device="cuda").to(td).contiguous()
+    rd = torch.zeros_like(qd)
+    s.elastic_step(qd, rd, dt, 3, wall="rigid")
+    torch.cuda.synchronize()
+    o = Oracle(xyz, etov, N, M)
+    qm, _ = elastic_step(o, o.from_bernstein(q), np.zeros((9, K, Np)), dt, 3, media, wall="rigid")
+    err = o.rel_l2(o.bernstein_values_at_quad(qd.double().cpu().numpy()), o.values_at_quad(qm))
+    tol = 1e-11 if dtype == "f64" else (2e-6 if N <= 6 else 2e-5)
+    assert np.all(err < tol), err
