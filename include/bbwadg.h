@@ -312,8 +312,9 @@ int bbwadg_elastic_update(bbwadg_ctx* ctx, const void* r, void* out, void* strea
  * [9][K][Np] of the context dtype, no overlap. weighted = 0 returns the right-hand side before
  * the media enter; weighted = 1 follows it with bbwadg_elastic_update (EC2 before
  * bbwadg_elastic_set_media) through a context-owned [9][K][Np] temporary, allocated on the first
- * such call. EINVAL for a bad wall or a negative or non-finite tau. The lift tables are built on
- * the first call. */
+ * such call. EINVAL for a bad wall or a negative or non-finite tau. The lift is the factored
+ * Bernstein lift of Section 4 (L_0 and a chain of 2D degree reductions); a face-position table
+ * is uploaded on the first call. */
 int bbwadg_elastic_rhs(bbwadg_ctx* ctx, const void* q, void* rhs, int32_t wall, double tau_v, double tau_s,
                        int32_t weighted, void* stream);
 

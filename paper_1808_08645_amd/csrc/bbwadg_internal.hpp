@@ -107,7 +107,6 @@ struct ElasticRhsArgs {
   const real* geo;       // [K][kGeoStride]
   const int32_t* conn;   // [K][4]
   const int32_t* fpos;   // [4][Nfp] volume position of face coefficient m of face f
-  const real* lift;      // [4][Np][Nfp] L^f = M^{-1} M_f in the Bernstein basis (reference face area 2)
   int64_t K;
   real tau_v, tau_s;
   int32_t wall;          // 0: traction-free, 1: rigid

@@ -12,8 +12,10 @@
 //    Bernstein polynomial of the coefficients with alpha_f = 0), neighbour coefficients read at the
 //    same face multi-index (element vertices are stored in ascending order, so a shared face lists
 //    its vertices in the same order on both sides), mirror states on walls;
-//  * lift: L^f = M^{-1} M_f as a dense Bernstein matrix per reference face (a first version;
-//    the acoustic kernel uses the sparse factorisation of Section 4).
+//  * lift: L^f = E_L L_0 (Section 4): L_0 = (2N+3)/2 I + N^2/2 E E^T on the face flux, then a
+//    chain of 2D degree reductions E^T, level i scaled by l_i = (-1)^i C(N, i)/(i + 1), and the
+//    coefficient alpha takes level alpha_f at its face multi-index. One face at a time, so the
+//    flux, the chain and its first reduction share one LDS region.
 #include "bbwadg_internal.hpp"
 
 namespace bbw {
@@ -25,12 +27,23 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// l_i = (-1)^i C(N, i) / (i + 1): factor of lift level i.
+__host__ __device__ constexpr double lift_level(int N, int i) {
+  double c = 1.0;
+  for (int j = 1; j <= i; ++j) c = c * (N - i + j) / j;
+  return (i % 2 ? -c : c) / (i + 1);
+}
+
 template <typename real, int N>
 struct ElRhsLayout {
-  static constexpr int NP = dimp(N), NQ = dimp(N - 1), NFP = dim2(N);
-  static constexpr int OFF_Q = 0, OFF_D = 9 * NP, OFF_R = OFF_D + 9 * NQ, OFF_F = OFF_R + 9 * NP,
-                       TOTAL = OFF_F + 4 * 9 * NFP;
-  static constexpr int TABLES = 16 * NP + 4 * 4 * NFP;
+  static constexpr int NP = dimp(N), NQ = dimp(N - 1), NFP = dim2(N), NT = dim2(N - 1);
+  // per wave: Qs [9][NP], Rs [9][NP], then a region used first for the degree N-1
+  // derivatives [9][NQ], then per face for the flux F [9][NFP], T = E^T F [9][NT] and the
+  // lift chain [9][NP] (level i of degree N - i at offset sum_{i' < i} dim2(N - i'))
+  static constexpr int OFF_Q = 0, OFF_R = 9 * NP, OFF_W = 18 * NP;
+  static constexpr int WSZ = 9 * NQ > 9 * (NFP + NT + NP) ? 9 * NQ : 9 * (NFP + NT + NP);
+  static constexpr int TOTAL = OFF_W + WSZ;
+  static constexpr int TABLES = 16 * NP + 4 * NP + 4 * 4 * NFP + 4 * NFP;
   static constexpr int per = TOTAL * (int)sizeof(real);
   static constexpr int WAVES = (61440 - TABLES) / per >= 4 ? 4 : ((61440 - TABLES) / per >= 1 ? (61440 - TABLES) / per : 1);
 };
@@ -40,13 +53,18 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
   using L = ElRhsLayout<real, N>;
   constexpr int NP = L::NP, NQ = L::NQ, NFP = L::NFP, WPB = L::WAVES;
   __shared__ real smem[WPB * L::TOTAL];
+  constexpr int NT = L::NT;
   __shared__ uint4 itab[NP];
+  __shared__ uint32_t lpos[NP];  // byte f: chain position of coefficient i for face f
   __shared__ int fpos[4 * NFP];
+  __shared__ int ftab[NFP];      // face position m at any degree: s | b2 << 8 (s = b1 + b2)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   real* const Qs = smem + wave * L::TOTAL + L::OFF_Q;
-  real* const Dn = smem + wave * L::TOTAL + L::OFF_D;
   real* const Rs = smem + wave * L::TOTAL + L::OFF_R;
-  real* const Fs = smem + wave * L::TOTAL + L::OFF_F;
+  real* const Dn = smem + wave * L::TOTAL + L::OFF_W;
+  real* const Fs = Dn;                 // [9][NFP]
+  real* const Ts = Dn + 9 * NFP;       // [9][NT]
+  real* const Cs = Ts + 9 * NT;        // [9][NP]
 
   // itab[i] for the multi-index a at graded position i (s = |a|, D(s) = (s+1)(s+2)/2):
   //   x: pos(a+e1) | pos(a+e3) << 16 (pos(a+e2) = pos(a+e1) + 1); y: pos(a-e1) | pos(a-e2) << 16;
@@ -64,8 +82,27 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
     t.z = (uint32_t)(a3 > 0 ? i - dd - d - 1 : 0) | ((uint32_t)a1 << 16) | ((uint32_t)a2 << 24);
     t.w = (uint32_t)a3 | ((uint32_t)d << 8);
     itab[i] = t;
+    // lift gather: face f's vertices in ascending order without f, (b0, b1, b2) of alpha on
+    // them; level j = alpha_f of degree N - j starts at sum_{i' < j} dim2(N - i')
+    const int al[4] = {N - d, a1, a2, a3};
+    uint32_t lp = 0;
+    for (int f = 0; f < 4; ++f) {
+      int vs[3], n = 0;
+      for (int v = 0; v < 4; ++v)
+        if (v != f) vs[n++] = v;
+      const int j = al[f], b1 = al[vs[1]], b2 = al[vs[2]], sb = b1 + b2;
+      int off = 0;
+      for (int q = 0; q < j; ++q) off += dim2(N - q);
+      lp |= (uint32_t)(off + sb * (sb + 1) / 2 + b2) << (8 * f);
+    }
+    lpos[i] = lp;
   }
   for (int i = threadIdx.x; i < 4 * NFP; i += 64 * WPB) fpos[i] = a.fpos[i];
+  for (int m = threadIdx.x; m < NFP; m += 64 * WPB) {
+    int sb = 0;
+    while ((sb + 1) * (sb + 2) / 2 <= m) ++sb;
+    ftab[m] = sb | ((m - sb * (sb + 1) / 2) << 8);
+  }
   __syncthreads();
 
   // the terms of the 9 outputs: (field, direction) pairs, up to 3 per output
@@ -115,73 +152,105 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
       if (a0 > 0) v += real(a0) * y[i];
       Rs[c * NP + i] = v / real(N);
     }
-    // fluxes on the face coefficients
-    for (int t = lane; t < 4 * NFP; t += 64) {
-      const int f = t / NFP, m = t - f * NFP;
-      const int po = fpos[f * NFP + m];
+    wsync();  // Dn is dead: its region holds the face work from here
+    for (int f = 0; f < 4; ++f) {
+      // flux on face f's coefficients
       const int cn = a.conn[4 * k + f];
-      real jv[3], js[6];
       const real* gf = geo + 9 + 4 * f;
       const real nx = gf[1], ny = gf[2], nz = gf[3];
-      if (cn >= 0) {
-        const int64_t k2 = cn >> 2;
-        const int pn = fpos[(cn & 3) * NFP + m];
+      for (int m = lane; m < NFP; m += 64) {
+        const int po = fpos[f * NFP + m];
+        real jv[3], js[6];
+        if (cn >= 0) {
+          const int64_t k2 = cn >> 2;
+          const int pn = fpos[(cn & 3) * NFP + m];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) jv[c] = a.q[((size_t)c * K + k2) * NP + pn] - Qs[c * NP + po];
+          for (int c = 0; c < 3; ++c) jv[c] = a.q[((size_t)c * K + k2) * NP + pn] - Qs[c * NP + po];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) js[c] = a.q[((size_t)(3 + c) * K + k2) * NP + pn] - Qs[(3 + c) * NP + po];
-      } else if (a.wall == 0) {  // traction-free: sigma+ = -sigma, v+ = v
+          for (int c = 0; c < 6; ++c) js[c] = a.q[((size_t)(3 + c) * K + k2) * NP + pn] - Qs[(3 + c) * NP + po];
+        } else if (a.wall == 0) {  // traction-free: sigma+ = -sigma, v+ = v
 #pragma unroll
-        for (int c = 0; c < 3; ++c) jv[c] = real(0);
+          for (int c = 0; c < 3; ++c) jv[c] = real(0);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) js[c] = real(-2) * Qs[(3 + c) * NP + po];
-      } else {  // rigid: v+ = -v, sigma+ = sigma
+          for (int c = 0; c < 6; ++c) js[c] = real(-2) * Qs[(3 + c) * NP + po];
+        } else {  // rigid: v+ = -v, sigma+ = sigma
 #pragma unroll
-        for (int c = 0; c < 3; ++c) jv[c] = real(-2) * Qs[c * NP + po];
+          for (int c = 0; c < 3; ++c) jv[c] = real(-2) * Qs[c * NP + po];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) js[c] = real(0);
+          for (int c = 0; c < 6; ++c) js[c] = real(0);
+        }
+        // A_n^T s = (sxx nx + sxy ny + sxz nz, sxy nx + syy ny + syz nz, sxz nx + syz ny + szz nz)
+        auto AnT = [&](const real* sg, real* o) {
+          o[0] = sg[0] * nx + sg[5] * ny + sg[4] * nz;
+          o[1] = sg[5] * nx + sg[1] * ny + sg[3] * nz;
+          o[2] = sg[4] * nx + sg[3] * ny + sg[2] * nz;
+        };
+        // A_n w = (nx w1, ny w2, nz w3, nz w2 + ny w3, nz w1 + nx w3, ny w1 + nx w2)
+        auto An = [&](const real* w, real* o) {
+          o[0] = nx * w[0];
+          o[1] = ny * w[1];
+          o[2] = nz * w[2];
+          o[3] = nz * w[1] + ny * w[2];
+          o[4] = nz * w[0] + nx * w[2];
+          o[5] = ny * w[0] + nx * w[1];
+        };
+        real ats[3], anv[6], atanv[3], anats[6];
+        AnT(js, ats);
+        An(jv, anv);
+        AnT(anv, atanv);
+        An(ats, anats);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fs[c * NFP + m] = real(0.5) * ats[c] + real(0.5) * a.tau_v * atanv[c];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Fs[(3 + c) * NFP + m] = real(0.5) * anv[c] + real(0.5) * a.tau_s * anats[c];
       }
-      // A_n^T s = (sxx nx + sxy ny + sxz nz, sxy nx + syy ny + syz nz, sxz nx + syz ny + szz nz)
-      auto AnT = [&](const real* s, real* o) {
-        o[0] = s[0] * nx + s[5] * ny + s[4] * nz;
-        o[1] = s[5] * nx + s[1] * ny + s[3] * nz;
-        o[2] = s[4] * nx + s[3] * ny + s[2] * nz;
-      };
-      // A_n w = (nx w1, ny w2, nz w3, nz w2 + ny w3, nz w1 + nx w3, ny w1 + nx w2)
-      auto An = [&](const real* w, real* o) {
-        o[0] = nx * w[0];
-        o[1] = ny * w[1];
-        o[2] = nz * w[2];
-        o[3] = nz * w[1] + ny * w[2];
-        o[4] = nz * w[0] + nx * w[2];
-        o[5] = ny * w[0] + nx * w[1];
-      };
-      real ats[3], anv[6], atanv[3], anats[6];
-      AnT(js, ats);
-      An(jv, anv);
-      AnT(anv, atanv);
-      An(ats, anats);
-      real* Ff = Fs + f * 9 * NFP;
+      wsync();
+      // T = (E^{N-1}_N)^T F at degree N - 1: (1/N) [(N - s) F_b + (b1 + 1) F_{b+e1} + (b2 + 1) F_{b+e2}]
+      for (int t = lane; t < 9 * NT; t += 64) {
+        const int c = t / NT, b = t - c * NT;
+        const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
+        const real* F = Fs + c * NFP;
+        Ts[c * NT + b] = (real(N - sb) * F[b] + real(b1 + 1) * F[b + sb + 1] + real(b2 + 1) * F[b + sb + 2]) / real(N);
+      }
+      wsync();
+      // level 0 = L_0 F = (2N+3)/2 F + N^2/2 E T, E T = (1/N) [(N - s) T_b + b1 T_{b-e1} + b2 T_{b-e2}]
+      for (int t = lane; t < 9 * NFP; t += 64) {
+        const int c = t / NFP, b = t - c * NFP;
+        const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
+        const real* T = Ts + c * NT;
+        real et = real(0);
+        if (sb < N) et += real(N - sb) * T[b];
+        if (b1 > 0) et += real(b1) * T[b - sb];
+        if (b2 > 0) et += real(b2) * T[b - sb - 1];
+        Cs[c * NP + b] = real(2 * N + 3) / real(2) * Fs[c * NFP + b] + real(N) / real(2) * et;
+      }
+      wsync();
+      // level i (degree n - 1, n = N - i + 1) = (l_i / l_{i-1}) (E^{n-1}_n)^T level i-1
+      int src = 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Ff[c * NFP + m] = real(0.5) * ats[c] + real(0.5) * a.tau_v * atanv[c];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) Ff[(3 + c) * NFP + m] = real(0.5) * anv[c] + real(0.5) * a.tau_s * anats[c];
+      for (int i = 1; i <= N; ++i) {
+        const int n = N - i + 1, cnt = dim2(n - 1), dst = src + dim2(n);
+        const real sc = real(lift_level(N, i) / lift_level(N, i - 1) / n);
+        for (int t = lane; t < 9 * cnt; t += 64) {
+          const int c = t / cnt, b = t - c * cnt;
+          const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
+          const real* C = Cs + c * NP + src;
+          Cs[c * NP + dst + b] = sc * (real(n - sb) * C[b] + real(b1 + 1) * C[b + sb + 1] + real(b2 + 1) * C[b + sb + 2]);
+        }
+        src = dst;
+        wsync();
+      }
+      // gather: coefficient alpha takes level alpha_f at its face multi-index
+      const real fsc = gf[0];
+      for (int t = lane; t < 9 * NP; t += 64) {
+        const int c = t / NP, i = t - c * NP;
+        Rs[c * NP + i] += fsc * Cs[c * NP + ((lpos[i] >> (8 * f)) & 255)];
+      }
+      wsync();
     }
-    wsync();
-    // lift: r[c][i] += sum_f Fscale_f sum_m L^f[i][m] F[f][c][m]
     for (int t = lane; t < 9 * NP; t += 64) {
       const int c = t / NP, i = t - c * NP;
-      real r = Rs[c * NP + i];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const real sc = geo[9 + 4 * f];
-        const real* Lf = a.lift + ((size_t)f * NP + i) * NFP;
-        const real* Ff = Fs + (f * 9 + c) * NFP;
-        real s = real(0);
-        for (int m = 0; m < NFP; ++m) s += Lf[m] * Ff[m];
-        r += sc * s;
-      }
-      a.out[((size_t)c * K + k) * NP + i] = r;
+      a.out[((size_t)c * K + k) * NP + i] = Rs[c * NP + i];
     }
     wsync();  // the slice is reused by the next element
   }

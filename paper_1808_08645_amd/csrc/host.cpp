@@ -317,7 +317,6 @@ struct bbwadg_ctx {
   void* d_el_rho = nullptr;     // [K][Mp] 1/rho
   void* d_el_lam = nullptr;     // [K][Mp] lambda
   void* d_el_mu = nullptr;      // [K][Mp] mu
-  void* d_el_lift = nullptr;    // [4][Np][Nfp] Bernstein lift (dtype)
   void* d_el_fpos = nullptr;    // [4][Nfp] int32
   void* d_el_tmp = nullptr;     // [9][K][Np] pre-update right-hand side (dtype)
   void* d_el_rhs = nullptr;     // [9][K][Np] weighted right-hand side of a time step (dtype)
@@ -351,8 +350,7 @@ void free_device(bbwadg_ctx* c) {
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
                    &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
                    &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_bwa,
-                   &c->d_adj_ones, &c->d_el_rho, &c->d_el_lam, &c->d_el_mu, &c->d_el_lift,
-                   &c->d_el_fpos, &c->d_el_tmp, &c->d_el_rhs};
+                   &c->d_adj_ones, &c->d_el_rho, &c->d_el_lam, &c->d_el_mu, &c->d_el_fpos, &c->d_el_tmp, &c->d_el_rhs};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -1487,55 +1485,34 @@ int bbwadg_misfit_gradient(bbwadg_ctx* c, const void* q0, double t0, double dt, 
 namespace {
 
 // Face coefficient m of face f <-> face multi-index (b0, b1, b2) on the face's vertices in
-// ascending local order, m = s(s+1)/2 + b2 with s = b1 + b2; and the Bernstein lift
-// L^f = M^{-1} M_f with (M_f)_{a,m} = int_f B_a B_m over a reference face of area 2.
+// ascending local order, m = s(s+1)/2 + b2 with s = b1 + b2: the volume position of that
+// coefficient (alpha_f = 0).
 int elastic_tables(bbwadg_ctx* c) {
-  if (c->d_el_lift) return 0;
-  const int N = c->N, Np = c->Np, Nfp = c->Nfp;
-  auto A = mi3_list(N);  // {a0, a1, a2, a3} in graded order
+  if (c->d_el_fpos) return 0;
+  const int N = c->N, Nfp = c->Nfp;
   std::vector<int32_t> fpos(4 * Nfp);
-  std::vector<std::array<int, 3>> fm(Nfp);
-  for (int s = 0; s <= N; ++s)
-    for (int b2 = 0; b2 <= s; ++b2) {
-      const int b1 = s - b2, m = s * (s + 1) / 2 + b2;
-      fm[m] = {N - s, b1, b2};
-    }
   for (int f = 0; f < 4; ++f) {
     int vs[3], n = 0;
     for (int v = 0; v < 4; ++v)
       if (v != f) vs[n++] = v;
-    for (int m = 0; m < Nfp; ++m) {
-      int al[4] = {0, 0, 0, 0};
-      for (int q = 0; q < 3; ++q) al[vs[q]] = fm[m][q];
-      fpos[f * Nfp + m] = dimp(al[1] + al[2] + al[3] - 1) + al[3] * (2 * (al[1] + al[2] + al[3]) + 3 - al[3]) / 2 + al[2];
-    }
-  }
-  std::vector<ld> Mm = bernstein_mass(N);
-  const ld base = 2.0L / (binoml(2 * N, N) * binoml(2 * N + 2, 2));
-  std::vector<double> lift((size_t)4 * Np * Nfp);
-  for (int f = 0; f < 4; ++f) {
-    int vs[3], n = 0;
-    for (int v = 0; v < 4; ++v)
-      if (v != f) vs[n++] = v;
-    for (int m = 0; m < Nfp; ++m) {
-      std::vector<ld> col(Np, 0.0L);
-      for (int j = 0; j < Np; ++j) {
-        if (A[j][f] != 0) continue;  // a_f = 0: on the face
-        ld cc = base;
-        for (int q = 0; q < 3; ++q) cc *= binoml(A[j][vs[q]] + fm[m][q], A[j][vs[q]]);
-        col[j] = cc;
+    for (int s = 0; s <= N; ++s)
+      for (int b2 = 0; b2 <= s; ++b2) {
+        const int b[3] = {N - s, s - b2, b2};
+        int al[4] = {0, 0, 0, 0};
+        for (int q = 0; q < 3; ++q) al[vs[q]] = b[q];
+        const int d = al[1] + al[2] + al[3];
+        fpos[f * Nfp + s * (s + 1) / 2 + b2] = dimp(d - 1) + al[3] * (2 * d + 3 - al[3]) / 2 + al[2];
       }
-      spd_solve(Mm, Np, col);
-      for (int i = 0; i < Np; ++i) lift[((size_t)f * Np + i) * Nfp + m] = (double)col[i];
-    }
   }
+  void* p = nullptr;
   int rc;
-  if ((rc = dmalloc(&c->d_el_fpos, fpos.size() * 4)) || (rc = upload(c->d_el_fpos, fpos.data(), fpos.size() * 4)) ||
-      (rc = dmalloc(&c->d_el_lift, lift.size() * c->rsz)))
+  if ((rc = dmalloc(&p, fpos.size() * 4))) return rc;
+  if ((rc = upload(p, fpos.data(), fpos.size() * 4))) {
+    (void)hipFree(p);
     return rc;
-  if (c->dtype == BBWADG_F64) return upload(c->d_el_lift, lift.data(), lift.size() * 8);
-  std::vector<float> lf(lift.begin(), lift.end());
-  return upload(c->d_el_lift, lf.data(), lf.size() * 4);
+  }
+  c->d_el_fpos = p;
+  return 0;
 }
 
 template <typename real>
@@ -1546,7 +1523,6 @@ int elastic_rhs_typed(bbwadg_ctx* c, const void* q, void* out, int32_t wall, dou
   a.geo = (const real*)c->d_geo;
   a.conn = (const int32_t*)c->d_conn;
   a.fpos = (const int32_t*)c->d_el_fpos;
-  a.lift = (const real*)c->d_el_lift;
   a.K = c->K;
   a.tau_v = (real)tau_v;
   a.tau_s = (real)tau_s;
