@@ -90,6 +90,11 @@ struct ElasticArgs {
   const real* mu;
   int64_t K;
   real cj[kMaxN + 1];
+  // optional low-storage RK stage in place of out (res != nullptr): res = rk_a res + dt u,
+  // q += rk_b res, u the update of r; res, q [9][K][Np]
+  real* res;
+  real* q;
+  real rk_a, rk_b, dt;
 };
 template <typename real>
 int launch_elastic_update(int N, int M, const ElasticArgs<real>& a, void* stream);

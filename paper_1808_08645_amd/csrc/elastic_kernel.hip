@@ -240,9 +240,22 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
         }
         wsync();
       }
-      for (int t = lane; t < G * NP; t += 64) {
-        const int cl = t / NP, i = t - cl * NP;
-        a.out[((size_t)(c0 + cl) * a.K + k) * NP + i] = LV[cl * LEV + i];
+      if (a.res) {  // a low-storage RK stage (uniform branch); res and q never alias
+        real* __restrict__ rs = a.res;
+        real* __restrict__ qs = a.q;
+#pragma unroll 4
+        for (int t = lane; t < G * NP; t += 64) {
+          const int cl = t / NP, i = t - cl * NP;
+          const size_t idx = ((size_t)(c0 + cl) * a.K + k) * NP + i;
+          const real r2 = a.rk_a * rs[idx] + a.dt * LV[cl * LEV + i];
+          rs[idx] = r2;
+          qs[idx] += a.rk_b * r2;
+        }
+      } else {
+        for (int t = lane; t < G * NP; t += 64) {
+          const int cl = t / NP, i = t - cl * NP;
+          a.out[((size_t)(c0 + cl) * a.K + k) * NP + i] = LV[cl * LEV + i];
+        }
       }
       wsync();  // the buffers are reused by the next group and element
     }

@@ -319,7 +319,7 @@ struct bbwadg_ctx {
   void* d_el_mu = nullptr;      // [K][Mp] mu
   void* d_el_fpos = nullptr;    // [4][Nfp] int32
   void* d_el_tmp = nullptr;     // [9][K][Np] pre-update right-hand side (dtype)
-  void* d_el_rhs = nullptr;     // [9][K][Np] weighted right-hand side of a time step (dtype)
+  void* d_el_rhs = nullptr;     // [9][K][Np] weighted right-hand side of a time step, N >= 8 (dtype)
 };
 
 namespace {
@@ -1516,6 +1516,33 @@ int elastic_tables(bbwadg_ctx* c) {
 }
 
 template <typename real>
+int elastic_update_typed(bbwadg_ctx* c, const void* r, void* out, void* res, void* q, double ra, double rb, double dt,
+                         void* stream) {
+  ElasticArgs<real> a{};
+  a.r = (const real*)r;
+  a.out = (real*)out;
+  a.rho_inv = (const real*)c->d_el_rho;
+  a.lam = (const real*)c->d_el_lam;
+  a.mu = (const real*)c->d_el_mu;
+  a.K = c->K;
+  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  a.res = (real*)res;
+  a.q = (real*)q;
+  a.rk_a = (real)ra;
+  a.rk_b = (real)rb;
+  a.dt = (real)dt;
+  return launch_elastic_update<real>(c->N, c->M, a, stream);
+}
+
+// The elastic update of r into out, or (res != nullptr) a low-storage RK stage from it.
+int elastic_update_launch(bbwadg_ctx* c, const void* r, void* out, void* res, void* q, double ra, double rb,
+                          double dt, void* stream) {
+  const int e = c->dtype == BBWADG_F64 ? elastic_update_typed<double>(c, r, out, res, q, ra, rb, dt, stream)
+                                       : elastic_update_typed<float>(c, r, out, res, q, ra, rb, dt, stream);
+  return e ? fail(BBWADG_EHIP, "elastic update launch: %s", hipGetErrorString((hipError_t)e)) : 0;
+}
+
+template <typename real>
 int elastic_rhs_typed(bbwadg_ctx* c, const void* q, void* out, int32_t wall, double tau_v, double tau_s, hipStream_t s) {
   ElasticRhsArgs<real> a{};
   a.q = (const real*)q;
@@ -1568,12 +1595,22 @@ int bbwadg_elastic_step(bbwadg_ctx* c, void* q, void* res, double dt, int32_t ns
   if (nsteps < 0) return fail(BBWADG_EINVAL, "nsteps must be >= 0");
   if (!c->d_el_rho) return fail(BBWADG_EC2, "elastic media not set (call bbwadg_elastic_set_media)");
   const int64_t n = (int64_t)9 * c->K * c->Np;
-  if (!c->d_el_rhs && (rc = dmalloc(&c->d_el_rhs, (size_t)n * c->rsz))) return rc;
+  // The RK bookkeeping rides on the update's final write for N <= 7; above, at the update's
+  // low occupancy, the extra read-modify-write is exposed (measured slower at N = 9) and the
+  // update writes Pi(r) for two lincomb passes instead.
+  const bool fused = c->N <= 7;
+  if (!c->d_el_tmp && (rc = dmalloc(&c->d_el_tmp, (size_t)n * c->rsz))) return rc;
+  if (!fused && !c->d_el_rhs && (rc = dmalloc(&c->d_el_rhs, (size_t)n * c->rsz))) return rc;
   hipStream_t s = (hipStream_t)stream;
   for (int32_t it = 0; it < nsteps; ++it)
     for (int st = 0; st < 5; ++st) {
-      // res = a_k res + dt R(q); q = q + b_k res
-      if ((rc = bbwadg_elastic_rhs(c, q, c->d_el_rhs, wall, tau_v, tau_s, 1, stream))) return rc;
+      // r = the right-hand side of q; res = a_k res + dt Pi(r), q = q + b_k res
+      if ((rc = bbwadg_elastic_rhs(c, q, c->d_el_tmp, wall, tau_v, tau_s, 0, stream))) return rc;
+      if (fused) {
+        if ((rc = elastic_update_launch(c, c->d_el_tmp, nullptr, res, q, kRkA[st], kRkB[st], dt, stream))) return rc;
+        continue;
+      }
+      if ((rc = elastic_update_launch(c, c->d_el_tmp, c->d_el_rhs, nullptr, nullptr, 0.0, 0.0, 0.0, stream))) return rc;
       int e = c->dtype == BBWADG_F64
                   ? launch_lincomb<double>((double*)res, (const double*)c->d_el_rhs, kRkA[st], dt, n, s)
                   : launch_lincomb<float>((float*)res, (const float*)c->d_el_rhs, kRkA[st], dt, n, s);
@@ -1643,30 +1680,7 @@ int bbwadg_elastic_update(bbwadg_ctx* c, const void* r, void* out, void* stream)
   if (!r || !out) return fail(BBWADG_EINVAL, "NULL state pointer");
   if (r == out) return fail(BBWADG_EINVAL, "r and out must not overlap");
   if (!c->d_el_rho) return fail(BBWADG_EC2, "elastic media not set (call bbwadg_elastic_set_media)");
-  int e;
-  if (c->dtype == BBWADG_F64) {
-    ElasticArgs<double> a{};
-    a.r = (const double*)r;
-    a.out = (double*)out;
-    a.rho_inv = (const double*)c->d_el_rho;
-    a.lam = (const double*)c->d_el_lam;
-    a.mu = (const double*)c->d_el_mu;
-    a.K = c->K;
-    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = c->tables.cj[j];
-    e = launch_elastic_update<double>(c->N, c->M, a, stream);
-  } else {
-    ElasticArgs<float> a{};
-    a.r = (const float*)r;
-    a.out = (float*)out;
-    a.rho_inv = (const float*)c->d_el_rho;
-    a.lam = (const float*)c->d_el_lam;
-    a.mu = (const float*)c->d_el_mu;
-    a.K = c->K;
-    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (float)c->tables.cj[j];
-    e = launch_elastic_update<float>(c->N, c->M, a, stream);
-  }
-  if (e) return fail(BBWADG_EHIP, "elastic update launch: %s", hipGetErrorString((hipError_t)e));
-  return 0;
+  return elastic_update_launch(c, r, out, nullptr, nullptr, 0.0, 0.0, 0.0, stream);
 }
 
 int bbwadg_adjoint_apply(bbwadg_ctx* c, const void* z, void* out, void* stream) {
