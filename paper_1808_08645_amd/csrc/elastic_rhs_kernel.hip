@@ -37,10 +37,15 @@ __host__ __device__ constexpr double lift_level(int N, int i) {
 template <typename real, int N>
 struct ElRhsLayout {
   static constexpr int NP = dimp(N), NQ = dimp(N - 1), NFP = dim2(N), NT = dim2(N - 1);
-  // per wave: Qs [9][NP], Rs [9][NP], then a region used first for the degree N-1
-  // derivatives [9][NQ], then per face for the flux F [9][NFP], T = E^T F [9][NT] and the
-  // lift chain [9][NP] (level i of degree N - i at offset sum_{i' < i} dim2(N - i'))
-  static constexpr int OFF_Q = 0, OFF_R = 9 * NP, OFF_W = 18 * NP;
+  // per wave: Qs [9][NP], the result Rs [9][NP] (unless REG), then a region used first for
+  // the degree N-1 derivatives [9][NQ], then per face for the flux F [9][NFP], T = E^T F
+  // [9][NT] and the lift chain [9][NP] (level i of degree N - i at offset
+  // sum_{i' < i} dim2(N - i')). With REG the result accumulates in registers instead (item
+  // t = lane + 64 j of the [9][NP] output in slot j): that frees LDS where LDS limits the
+  // wavefronts per CU (FP64 from N = 5, FP32 from N = 6; below, the registers cost more
+  // occupancy than the LDS does, as measured on MI355X).
+  static constexpr bool REG = sizeof(real) == 8 ? N >= 5 : N >= 6;
+  static constexpr int OFF_Q = 0, OFF_R = 9 * NP, OFF_W = REG ? 9 * NP : 18 * NP, RJ = (9 * NP + 63) / 64;
   static constexpr int WSZ = 9 * NQ > 9 * (NFP + NT + NP) ? 9 * NQ : 9 * (NFP + NT + NP);
   static constexpr int TOTAL = OFF_W + WSZ;
   static constexpr int TABLES = 16 * NP + 4 * NP + 4 * 4 * NFP + 4 * NFP;
@@ -60,7 +65,7 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
   __shared__ int ftab[NFP];      // face position m at any degree: s | b2 << 8 (s = b1 + b2)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   real* const Qs = smem + wave * L::TOTAL + L::OFF_Q;
-  real* const Rs = smem + wave * L::TOTAL + L::OFF_R;
+  real* const Rs = smem + wave * L::TOTAL + L::OFF_R;  // used only without REG
   real* const Dn = smem + wave * L::TOTAL + L::OFF_W;
   real* const Fs = Dn;                 // [9][NFP]
   real* const Ts = Dn + 9 * NFP;       // [9][NT]
@@ -143,14 +148,22 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
     }
     wsync();
     // elevation to degree N: (E y)_a = sum_{j: a_j > 0} (a_j / N) y_{a - e_j}
-    for (int t = lane; t < 9 * NP; t += 64) {
-      const int c = t / NP, i = t - c * NP;
-      const uint4 e = itab[i];
-      const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = N - (int)(e.w >> 8);
-      const real* y = Dn + c * NQ;
-      real v = real(a1) * y[e.y & 0xFFFF] + real(a2) * y[e.y >> 16] + real(a3) * y[e.z & 0xFFFF];
-      if (a0 > 0) v += real(a0) * y[i];
-      Rs[c * NP + i] = v / real(N);
+    real racc[L::REG ? L::RJ : 1];
+    constexpr int UNR = L::REG ? L::RJ : 1;  // the LDS variant keeps rolled loops (fewer registers)
+#pragma unroll UNR
+    for (int j = 0; j < L::RJ; ++j) {
+      const int t = lane + 64 * j;
+      if constexpr (L::REG) racc[j] = real(0);
+      if (t < 9 * NP) {
+        const int c = t / NP, i = t - c * NP;
+        const uint4 e = itab[i];
+        const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = N - (int)(e.w >> 8);
+        const real* y = Dn + c * NQ;
+        real v = real(a1) * y[e.y & 0xFFFF] + real(a2) * y[e.y >> 16] + real(a3) * y[e.z & 0xFFFF];
+        if (a0 > 0) v += real(a0) * y[i];
+        if constexpr (L::REG) racc[j] = v / real(N);
+        else Rs[t] = v / real(N);  // t = c NP + i
+      }
     }
     wsync();  // Dn is dead: its region holds the face work from here
     for (int f = 0; f < 4; ++f) {
@@ -242,15 +255,26 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
       }
       // gather: coefficient alpha takes level alpha_f at its face multi-index
       const real fsc = gf[0];
-      for (int t = lane; t < 9 * NP; t += 64) {
-        const int c = t / NP, i = t - c * NP;
-        Rs[c * NP + i] += fsc * Cs[c * NP + ((lpos[i] >> (8 * f)) & 255)];
+#pragma unroll UNR
+      for (int j = 0; j < L::RJ; ++j) {
+        const int t = lane + 64 * j;
+        if (t < 9 * NP) {
+          const int c = t / NP, i = t - c * NP;
+          const real g = fsc * Cs[c * NP + ((lpos[i] >> (8 * f)) & 255)];
+          if constexpr (L::REG) racc[j] += g;
+          else Rs[t] += g;
+        }
       }
       wsync();
     }
-    for (int t = lane; t < 9 * NP; t += 64) {
-      const int c = t / NP, i = t - c * NP;
-      a.out[((size_t)c * K + k) * NP + i] = Rs[c * NP + i];
+#pragma unroll UNR
+    for (int j = 0; j < L::RJ; ++j) {
+      const int t = lane + 64 * j;
+      if (t < 9 * NP) {
+        const int c = t / NP, i = t - c * NP;
+        if constexpr (L::REG) a.out[((size_t)c * K + k) * NP + i] = racc[j];
+        else a.out[((size_t)c * K + k) * NP + i] = Rs[t];
+      }
     }
     wsync();  // the slice is reused by the next element
   }
