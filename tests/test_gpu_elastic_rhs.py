@@ -141,3 +141,44 @@ def test_elastic_step_matches_oracle(bb, N, M, dtype):
     err = o.rel_l2(o.bernstein_values_at_quad(qd.double().cpu().numpy()), o.values_at_quad(qm))
     tol = 1e-11 if dtype == "f64" else (2e-6 if N <= 6 else 2e-5)
     assert np.all(err < tol), err
+
+
+def _energy(o, qb, rho_inv, lam, mu):
+    """1/2 int rho |v|^2 + sigma : C^{-1} sigma over the mesh for media constant per element
+    (Voigt shear components are engineering strains: sigma_s = mu gamma_s)."""
+    V = o.bernstein_values_at_quad(qb)  # [9, K, nq]
+    wJ = o.mesh.J[:, None] * o.wq[None, :]
+    rho = 1.0 / rho_inv[:, :1]
+    kin = rho * np.sum(V[:3] ** 2, axis=0)
+    lam, mu = lam[:, :1], mu[:, :1]
+    tr = V[3] + V[4] + V[5]
+    normal = (np.sum(V[3:6] ** 2, axis=0) - lam / (3.0 * lam + 2.0 * mu) * tr ** 2) / (2.0 * mu)
+    shear = np.sum(V[6:9] ** 2, axis=0) / mu
+    return 0.5 * float(np.sum(wJ * (kin + normal + shear)))
+
+
+@pytest.mark.parametrize("N", [3, 5])
+@pytest.mark.parametrize("wall", ["free", "rigid"])
+def test_elastic_step_energy_never_grows(bb, N, wall):
+    """Media constant per element (M = 0, where the weight-adjusted mass is the exact weighted
+    mass): the discrete energy of the device time steps is non-increasing, and the penalty
+    fluxes make it decrease (energy stability of the scheme, any mesh size)."""
+    import torch
+    print(f"[elastic energy] N={N} {wall}", flush=True)
+    xyz, etov = _mesh(2, 48, 9)
+    s = bb.Solver(xyz, etov, N, 0)
+    rng = np.random.default_rng(150 + N)
+    K = s.K
+    rho_inv, lam, mu = rng.uniform(0.5, 1.5, (K, 1)), rng.uniform(0.5, 2.0, (K, 1)), rng.uniform(0.3, 1.0, (K, 1))
+    s.elastic_set_media(rho_inv, lam, mu)
+    o = Oracle(xyz, etov, N, 0)
+    q = torch.as_tensor(rng.standard_normal((9, K, s.Np)), device="cuda").contiguous()
+    res = torch.zeros_like(q)
+    dt = 0.02 / (N + 1) ** 2
+    e = [_energy(o, q.cpu().numpy(), rho_inv, lam, mu)]
+    for _ in range(8):
+        s.elastic_step(q, res, dt, 5, wall=wall)
+        e.append(_energy(o, q.cpu().numpy(), rho_inv, lam, mu))
+    e = np.array(e)
+    assert np.all(np.diff(e) <= 1e-12 * e[0]), e
+    assert e[-1] < 0.999 * e[0] and e[-1] > 0.05 * e[0], e
