@@ -36,17 +36,16 @@ __host__ __device__ constexpr double lift_level(int N, int i) {
 
 template <typename real, int N>
 struct ElRhsLayout {
-  static constexpr int NP = dimp(N), NQ = dimp(N - 1), NFP = dim2(N), NT = dim2(N - 1);
+  static constexpr int NP = dimp(N), NQ = dimp(N - 1), NFP = dim2(N);
   // per wave: Qs [9][NP], the result Rs [9][NP] (unless REG), then a region used first for
-  // the degree N-1 derivatives [9][NQ], then per face for the flux F [9][NFP], T = E^T F
-  // [9][NT] and the lift chain [9][NP] (level i of degree N - i at offset
-  // sum_{i' < i} dim2(N - i')). With REG the result accumulates in registers instead (item
+  // the degree N-1 derivatives [9][NQ], then per face for the flux F [9][NFP] and the lift
+  // chain [9][NP] (level i of degree N - i at offset sum_{i' < i} dim2(N - i')). With REG the result accumulates in registers instead (item
   // t = lane + 64 j of the [9][NP] output in slot j): that frees LDS where LDS limits the
   // wavefronts per CU (FP64 from N = 5, FP32 from N = 6; below, the registers cost more
   // occupancy than the LDS does, as measured on MI355X).
   static constexpr bool REG = sizeof(real) == 8 ? N >= 5 : N >= 6;
   static constexpr int OFF_Q = 0, OFF_R = 9 * NP, OFF_W = REG ? 9 * NP : 18 * NP, RJ = (9 * NP + 63) / 64;
-  static constexpr int WSZ = 9 * NQ > 9 * (NFP + NT + NP) ? 9 * NQ : 9 * (NFP + NT + NP);
+  static constexpr int WSZ = 9 * NQ > 9 * (NFP + NP) ? 9 * NQ : 9 * (NFP + NP);
   static constexpr int TOTAL = OFF_W + WSZ;
   static constexpr int TABLES = 16 * NP + 4 * NP + 4 * 4 * NFP + 4 * NFP;
   static constexpr int per = TOTAL * (int)sizeof(real);
@@ -58,7 +57,6 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
   using L = ElRhsLayout<real, N>;
   constexpr int NP = L::NP, NQ = L::NQ, NFP = L::NFP, WPB = L::WAVES;
   __shared__ real smem[WPB * L::TOTAL];
-  constexpr int NT = L::NT;
   __shared__ uint4 itab[NP];
   __shared__ uint32_t lpos[NP];  // byte f: chain position of coefficient i for face f
   __shared__ int fpos[4 * NFP];
@@ -68,8 +66,7 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
   real* const Rs = smem + wave * L::TOTAL + L::OFF_R;  // used only without REG
   real* const Dn = smem + wave * L::TOTAL + L::OFF_W;
   real* const Fs = Dn;                 // [9][NFP]
-  real* const Ts = Dn + 9 * NFP;       // [9][NT]
-  real* const Cs = Ts + 9 * NT;        // [9][NP]
+  real* const Cs = Dn + 9 * NFP;       // [9][NP]
 
   // itab[i] for the multi-index a at graded position i (s = |a|, D(s) = (s+1)(s+2)/2):
   //   x: pos(a+e1) | pos(a+e3) << 16 (pos(a+e2) = pos(a+e1) + 1); y: pos(a-e1) | pos(a-e2) << 16;
@@ -218,24 +215,21 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
         for (int c = 0; c < 6; ++c) Fs[(3 + c) * NFP + m] = real(0.5) * anv[c] + real(0.5) * a.tau_s * anats[c];
       }
       wsync();
-      // T = (E^{N-1}_N)^T F at degree N - 1: (1/N) [(N - s) F_b + (b1 + 1) F_{b+e1} + (b2 + 1) F_{b+e2}]
-      for (int t = lane; t < 9 * NT; t += 64) {
-        const int c = t / NT, b = t - c * NT;
-        const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
-        const real* F = Fs + c * NFP;
-        Ts[c * NT + b] = (real(N - sb) * F[b] + real(b1 + 1) * F[b + sb + 1] + real(b2 + 1) * F[b + sb + 2]) / real(N);
-      }
-      wsync();
-      // level 0 = L_0 F = (2N+3)/2 F + N^2/2 E T, E T = (1/N) [(N - s) T_b + b1 T_{b-e1} + b2 T_{b-e2}]
+      // level 0 = L_0 F = (2N+3)/2 F + N^2/2 E E^T F in one pass, with E^T F at degree N - 1,
+      //   (E^T F)_x = (1/N) [(N - |x|) F_x + (x1 + 1) F_{x+e1} + (x2 + 1) F_{x+e2}],
+      //   (E y)_b = (1/N) [(N - |b|) y_b + b1 y_{b-e1} + b2 y_{b-e2}]
       for (int t = lane; t < 9 * NFP; t += 64) {
         const int c = t / NFP, b = t - c * NFP;
         const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
-        const real* T = Ts + c * NT;
-        real et = real(0);
-        if (sb < N) et += real(N - sb) * T[b];
-        if (b1 > 0) et += real(b1) * T[b - sb];
-        if (b2 > 0) et += real(b2) * T[b - sb - 1];
-        Cs[c * NP + b] = real(2 * N + 3) / real(2) * Fs[c * NFP + b] + real(N) / real(2) * et;
+        const real* F = Fs + c * NFP;
+        auto etf = [&](int x, int sx, int x2) {  // N (E^T F)_x
+          return real(N - sx) * F[x] + real(sx - x2 + 1) * F[x + sx + 1] + real(x2 + 1) * F[x + sx + 2];
+        };
+        real e = real(0);
+        if (sb < N) e += real(N - sb) * etf(b, sb, b2);
+        if (b1 > 0) e += real(b1) * etf(b - sb, sb - 1, b2);
+        if (b2 > 0) e += real(b2) * etf(b - sb - 1, sb - 1, b2 - 1);
+        Cs[c * NP + b] = real(2 * N + 3) / real(2) * F[b] + e / real(2);  // N^2/2 (1/N) (1/N) N e
       }
       wsync();
       // level i (degree n - 1, n = N - i + 1) = (l_i / l_{i-1}) (E^{n-1}_n)^T level i-1
