@@ -48,7 +48,8 @@ enum {
   BBWADG_OK = 0,
   BBWADG_EINVAL = -1, /* bad argument: range, NULL pointer, dtype, host-only context */
   BBWADG_EMESH = -2,  /* non-conforming mesh, face shared by > 2 elements, degenerate element */
-  BBWADG_EC2 = -3,    /* c^2 not set, non-finite, or not positive at a check point */
+  BBWADG_EC2 = -3,    /* c^2 (or an elastic medium) not set, non-finite, or not positive
+                         everywhere on an element (see bbwadg_set_c2_policy) */
   BBWADG_ENOMEM = -4, /* host or device allocation failed */
   BBWADG_EHIP = -5    /* HIP runtime or kernel launch error */
 };
@@ -56,6 +57,7 @@ enum {
 enum { BBWADG_F64 = 0, BBWADG_F32 = 1 };
 enum { BBWADG_BC_P0 = 0, BBWADG_BC_RIGID = 1 };
 enum { BBWADG_DEVICE = 0, BBWADG_HOST_ONLY = 1 };
+enum { BBWADG_C2_REQUIRE_POSITIVE = 0, BBWADG_C2_ACCEPT_NONPOSITIVE = 1 };
 
 typedef struct bbwadg_ctx bbwadg_ctx;
 
@@ -125,16 +127,41 @@ int bbwadg_project_samples(const bbwadg_ctx* ctx, int32_t degree, int64_t k0, in
 
 /* c^2 setup (paper Section 5: c^2 replaced by its per-element L^2 projection onto P^M).
  * bbwadg_project_c2 samples the callback c2(x, y, z, user) at the projection points,
- * projects in FP64, checks positivity at the projection points (EC2 otherwise), stores
- * the coefficients in the context and, if c2_out != NULL, copies them as dtype into the
- * device buffer c2_out [K][Mp] on `stream`. Stream-ordered before later rhs/step calls. */
+ * projects in FP64, checks the result like bbwadg_set_c2, stores the coefficients in the
+ * context and, if c2_out != NULL, copies them as dtype into the device buffer c2_out
+ * [K][Mp] on `stream`. Stream-ordered before later rhs/step calls. */
 int bbwadg_project_c2(bbwadg_ctx* ctx, double (*c2)(double x, double y, double z, void* user),
                       void* user, void* c2_out, void* stream);
 
 /* Inject per-element c^2 Bernstein coefficients host FP64 [K][Mp] (e.g. shared data for
- * parity runs). EC2 if any value is non-finite or c^2_M is not positive at a check point.
- * The device copy is refreshed on the next rhs/step call. */
+ * parity runs). The device copy is refreshed on the next rhs/step call.
+ * Check (Section 3: the weight-adjusted scheme is energy stable for a positive weight;
+ * Section 2: Bernstein polynomials are a nonnegative partition of unity): an element's
+ * c^2_M is accepted as positive when all its coefficients are > 0 (the polynomial lies in
+ * their convex hull); otherwise its tetrahedron is bisected along the longest edge, with
+ * the coefficients of the halves from de Casteljau subdivision, until every piece has
+ * positive coefficients (positive), a piece has a vertex value <= 0 (not positive), or
+ * 4096 pieces were visited (undecided). Under BBWADG_C2_REQUIRE_POSITIVE (the default)
+ * any element not positive or undecided gives EC2 and nothing is stored. EC2 as well for a
+ * non-finite value. */
 int bbwadg_set_c2(bbwadg_ctx* ctx, const double* c2_coef);
+
+/* Policy of bbwadg_set_c2 / bbwadg_project_c2 / bbwadg_elastic_set_media for a weight that
+ * is not positive everywhere: BBWADG_C2_REQUIRE_POSITIVE (default, EC2) or
+ * BBWADG_C2_ACCEPT_NONPOSITIVE (stored anyway; the energy bound of the scheme is then lost
+ * and the counts below say on how many elements). EINVAL for another value. */
+int bbwadg_set_c2_policy(bbwadg_ctx* ctx, int32_t policy);
+
+/* Counts for the stored c^2_M: elements with a value <= 0 and elements left undecided (see
+ * bbwadg_set_c2). EC2 if none is set. Either pointer may be NULL. */
+int bbwadg_c2_positivity(const bbwadg_ctx* ctx, int64_t* n_nonpositive, int64_t* n_undecided);
+
+/* The same classification for n arbitrary sets of degree-`degree` Bernstein coefficients
+ * host FP64 [n][dimp(degree)] (graded order), no context needed: counts of sets not
+ * positive / undecided, and the first such set (-1 if none). EINVAL for a bad degree (0..13)
+ * or n < 0, EC2 for a non-finite value. Any output pointer may be NULL. */
+int bbwadg_bernstein_positivity(int32_t degree, int64_t n, const double* coef, int64_t* n_nonpositive,
+                                int64_t* n_undecided, int64_t* first);
 
 /* Read back the stored c^2 coefficients, host FP64 [K][Mp]. EC2 if none is set. */
 int bbwadg_get_c2(const bbwadg_ctx* ctx, double* c2_coef);
@@ -211,7 +238,7 @@ int bbwadg_project_fn(bbwadg_ctx* ctx, double (*fn)(double x, double y, double z
  * dp/dt = P_q diag(c^2(x_q)) V_q r_p with V_q the degree-N Bernstein basis at the points of
  * the collapsed Gauss-Jacobi rule with n = floor((2N+M+2)/2) points per direction (exact to
  * degree 2N+M) and P_q = M^{-1} V_q^T W, applied as dense products on the FP64 matrix cores.
- * With c^2_M at the points it equals the fast Bernstein update (paper Theorem 5.1); with the
+ * With c^2_M at the points it equals the fast Bernstein update (paper Theorem 5.3); with the
  * true c^2 at the points it is the quadrature WADG the paper compares against. FP64 device
  * contexts only (EINVAL otherwise). The point values take K * 16 ceil(nq/16) doubles of
  * device memory, allocated by the first bbwadg_dense_set_c2 together with the tables. */
@@ -280,18 +307,21 @@ int bbwadg_adjoint_apply(bbwadg_ctx* ctx, const void* z, void* out, void* stream
 
 /* The weight-adjusted update on its own (paper Section 5, the update kernel of Table am1):
  * out = Pi_N(c^2_M r), the product with c^2_M exact in degree N + M (eq. mcoeff) and Pi_N the
- * telescoped projection (Theorem 5.1). r, out: device [K][Np] of the context dtype, no
+ * telescoped projection (Theorem 5.3). r, out: device [K][Np] of the context dtype, no
  * overlap. EC2 without c^2. The fused stage kernel computes the same update internally. */
 int bbwadg_wadg_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
 
-/* ---- elastic weight-adjusted update (paper Section 2.2, eq. ewadg) ----------------------
+/* ---- elastic weight-adjusted update (paper Section 3.2, eq. ewadg) ----------------------
  * The velocity-stress system rho v_t = sum_i A_i^T d sigma/dx_i, C^{-1} sigma_t = sum_i A_i
  * dv/dx_i with isotropic C (Lame parameters lambda, mu). Its weighted mass matrices are
  * replaced by the weight-adjusted inverse (I (x) M^{-1}) M_C (I (x) M^{-1}) (and M_{1/rho}
  * for the velocity), applied with the context's N, M and telescoped projection. */
 
 /* Media: host FP64 Bernstein coefficients [K][Mp] of degree M of 1/rho, lambda and mu (e.g.
- * projections from bbwadg_project_samples with degree M), copied. EINVAL if not finite. */
+ * projections from bbwadg_project_samples with degree M), copied. The mass-matrix weights
+ * 1/rho, mu and 3 lambda + 2 mu must be positive everywhere (the check of bbwadg_set_c2,
+ * under the same policy); all three are checked before any is uploaded, and on an error
+ * the previous media stay in place. EC2 for a non-finite or not positive medium. */
 int bbwadg_elastic_set_media(bbwadg_ctx* ctx, const double* rho_inv, const double* lam, const double* mu);
 
 /* out = the weight-adjusted update of the DG right-hand side r, both device [9][K][Np] of the
@@ -299,11 +329,11 @@ int bbwadg_elastic_set_media(bbwadg_ctx* ctx, const double* rho_inv, const doubl
  *   out_v_i = Pi_N(rho^{-1} r_v_i),  out_sigma_i = Pi_N(lambda tr r_sigma + 2 mu r_sigma_i)
  *   (i = xx, yy, zz),  out_sigma_s = Pi_N(mu r_sigma_s)  (s = yz, xz, xy),
  * each product exact in degree N + M (eq. mcoeff) and each Pi_N the telescoped projection
- * (Theorem 5.1): 12 products and 9 scalar projections per element. EC2 before
+ * (Theorem 5.3): 12 products and 9 scalar projections per element. EC2 before
  * bbwadg_elastic_set_media. */
 int bbwadg_elastic_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
 
-/* The elastic DG right-hand side (paper Section 2.2, the semi-discrete form after eq. ewave)
+/* The elastic DG right-hand side (paper Section 3.2, the semi-discrete form after eq. ewave)
  * with upwind-type penalty fluxes, A_n = sum_i n_i A_i on each face:
  *   r_v = sum_i A_i^T d sigma/dx_i + sum_f (J_f/J) L^f F_v,  F_v = A_n^T [[sigma]]/2 + tau_v/2 A_n^T A_n [[v]]
  *   r_s = sum_i A_i   d v/dx_i     + sum_f (J_f/J) L^f F_s,  F_s = A_n [[v]]/2     + tau_s/2 A_n A_n^T [[sigma]]
@@ -332,8 +362,8 @@ int bbwadg_elastic_step(bbwadg_ctx* ctx, void* q, void* res, double dt, int32_t 
 int32_t bbwadg_coef_index(int32_t a1, int32_t a2, int32_t a3);
 
 /* c_j of the telescoped projection P^{N+M}_N = sum_j c_j E^N_{N-j}(E^N_{N-j})^T
- * (E^{N+M}_N)^T (paper Theorem 5.1, Table 1), host double[N+1]. With M < 0 returns the
- * coefficients of the inverse mass matrix representation (paper Theorem 5.2, Table 2).
+ * (E^{N+M}_N)^T (paper Theorem 5.3, Table 1), host double[N+1]. With M < 0 returns the
+ * coefficients of the inverse mass matrix representation (paper Theorem 5.5, Table 2).
  * 1 <= N <= 9, -1 <= M <= 9. */
 int bbwadg_projection_coefficients(int32_t N, int32_t M, double* cj_out);
 

@@ -17,7 +17,7 @@ eq. (WADGform) and (pwadg)) in an orthonormal modal basis with dense matrices:
 * the 5-stage, 2N-storage fourth-order Runge-Kutta scheme of Carpenter and Kennedy.
 
 It shares no code with the HIP path. Bernstein coefficients enter and leave only
-through ``bernstein.py``, which evaluates the Bernstein basis from its definition
+through ``basis.py``, which evaluates the Bernstein basis from its definition
 (paper Section 2).
 """
 from .quadrature import gauss_jacobi, tet_rule, tri_rule  # noqa: F401

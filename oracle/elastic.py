@@ -1,6 +1,6 @@
 """Weight-adjusted update of the elastic velocity-stress system (test infrastructure only).
 
-Paper Section 2.2, eq. (ewadg): the weighted mass matrices of rho v_t = ... and
+Paper Section 3.2, eq. (ewadg): the weighted mass matrices of rho v_t = ... and
 C^{-1} sigma_t = ... are replaced by the weight-adjusted inverses M^{-1} M_{1/rho} and
 (I (x) M^{-1}) M_C (I (x) M^{-1}); applied to the DG right-hand side r = (r_v, r_sigma) per
 element this is, with isotropic C (Lame lambda, mu; Voigt order xx, yy, zz, yz, xz, xy),
@@ -40,7 +40,7 @@ def elastic_update(o: Oracle, R, rho_inv, lam, mu):
     return out @ o.Pq.T
 
 
-# The matrices A_i of the velocity-stress system (paper Section 2.2, eq. ewave), stress in the
+# The matrices A_i of the velocity-stress system (paper Section 3.2, eq. ewave), stress in the
 # Voigt order xx, yy, zz, yz, xz, xy.
 A_MATS = np.zeros((3, 6, 3))
 A_MATS[0, 0, 0] = A_MATS[0, 4, 2] = A_MATS[0, 5, 1] = 1.0

@@ -32,7 +32,7 @@ EXPORTS = (
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
     "bbwadg_elastic_rhs", "bbwadg_elastic_step",
-    "bbwadg_wadg_update",
+    "bbwadg_wadg_update", "bbwadg_set_c2_policy", "bbwadg_c2_positivity", "bbwadg_bernstein_positivity",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
     "bbwadg_sur_train_step",
@@ -113,6 +113,9 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_elastic_rhs": (C.c_int, [vp, vp, vp, i32, dbl, dbl, i32, vp]),
         "bbwadg_elastic_step": (C.c_int, [vp, vp, vp, dbl, i32, i32, dbl, dbl, vp]),
         "bbwadg_wadg_update": (C.c_int, [vp, vp, vp, vp]),
+        "bbwadg_set_c2_policy": (C.c_int, [vp, i32]),
+        "bbwadg_c2_positivity": (C.c_int, [vp, pi64, pi64]),
+        "bbwadg_bernstein_positivity": (C.c_int, [i32, i64, pd, pi64, pi64, pi64]),
         "bbwadg_sur_create": (C.c_int, [i32, i32, i32, C.c_uint64, C.POINTER(vp)]),
         "bbwadg_sur_destroy": (C.c_int, [vp]),
         "bbwadg_sur_num_params": (C.c_int64, [vp]),
@@ -161,6 +164,16 @@ def projection_coefficients(N: int, M: int) -> np.ndarray:
     out = np.zeros(N + 1)
     _check(lib.bbwadg_projection_coefficients(N, M, _dptr(out)))
     return out
+
+
+def bernstein_positivity(degree: int, coef) -> tuple:
+    """(not positive, undecided, first such set or -1) over sets of degree-`degree` Bernstein
+    coefficients [n, dimp(degree)] (bbwadg_bernstein_positivity)."""
+    lib = load_library()
+    c = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1, dimp(degree))
+    a, b, f = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib.bbwadg_bernstein_positivity(int(degree), c.shape[0], _dptr(c), C.byref(a), C.byref(b), C.byref(f)))
+    return a.value, b.value, f.value
 
 
 class Solver:
@@ -288,6 +301,17 @@ class Solver:
         if c.shape != (self.K, self.Mp):
             raise ValueError(f"c2 coefficients must be [{self.K}, {self.Mp}]")
         _check(self._lib.bbwadg_set_c2(self._ctx, _dptr(c)))
+
+    def set_c2_policy(self, accept_nonpositive: bool):
+        """Accept a c^2_M (or elastic medium) that is not positive everywhere (True), or reject
+        it with EC2 (False, the default)."""
+        _check(self._lib.bbwadg_set_c2_policy(self._ctx, 1 if accept_nonpositive else 0))
+
+    def c2_positivity(self) -> tuple:
+        """(elements where the stored c^2_M takes a value <= 0, elements left undecided)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(self._lib.bbwadg_c2_positivity(self._ctx, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def get_c2(self) -> np.ndarray:
         out = np.empty((self.K, self.Mp))

@@ -1,4 +1,4 @@
-// Weight-adjusted update of the elastic velocity-stress system (paper Section 2.2, eq. ewadg):
+// Weight-adjusted update of the elastic velocity-stress system (paper Section 3.2, eq. ewadg):
 // with the DG right-hand side r = (r_v, r_sigma) before the weight adjustment, the update is
 //   v'_i     = Pi_N(rho^{-1} r_v_i)                         i = 1, 2, 3
 //   sigma'_i = Pi_N(lambda tr(r_sigma) + 2 mu r_sigma_i)     i = xx, yy, zz
@@ -6,7 +6,7 @@
 // (isotropic C, Voigt order xx, yy, zz, yz, xz, xy), i.e. the matrix-weighted weight-adjusted
 // inverse (I (x) M^{-1}) M_C (I (x) M^{-1}) applied as scalar Bernstein products of degree
 // N + M (eq. mcoeff) followed by 9 scalar projections: M one-degree reductions to degree N
-// and the telescoped projection sum_j c_j E^N_{N-j} (E^N_{N-j})^T (Theorem 5.1).
+// and the telescoped projection sum_j c_j E^N_{N-j} (E^N_{N-j})^T (Theorem 5.3).
 //
 // One wavefront per element (grid-stride over elements), everything in its LDS slice; the 9
 // components go through the projection in groups (see ElasticLayout).

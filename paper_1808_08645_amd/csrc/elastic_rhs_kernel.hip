@@ -1,5 +1,5 @@
 // DG right-hand side of the elastic velocity-stress system before the weight adjustment
-// (paper Section 2.2, the semi-discrete form after eq. ewave), isotropic or not (the media
+// (paper Section 3.2, the semi-discrete form after eq. ewave), isotropic or not (the media
 // enter only through the weight-adjusted update that follows):
 //   r_v = sum_i A_i^T d sigma/dx_i + sum_f Fscale_f L^f F_v,  F_v = A_n^T [[sigma]]/2 + tau_v A_n^T A_n [[v]]/2
 //   r_s = sum_i A_i  d v/dx_i      + sum_f Fscale_f L^f F_s,  F_s = A_n [[v]]/2 + tau_s A_n A_n^T [[sigma]]/2

@@ -66,17 +66,102 @@ std::vector<std::array<int, 4>> mi3_list(int n) {
   return out;
 }
 
+// ----------------------------------------------------------------- positivity
+// Sign of a degree-m Bernstein polynomial on its tetrahedron. The Bernstein basis is a
+// nonnegative partition of unity (Section 2), so the polynomial lies between its smallest
+// and largest coefficient on the element, and the coefficient at a vertex (alpha = m e_i)
+// is the value there. When neither decides, the tetrahedron is bisected at the midpoint of
+// its longest edge (measured in barycentric coordinates); the coefficients of the two
+// halves follow from univariate de Casteljau subdivision at t = 1/2 along that edge, and
+// both halves are tested again. Returns +1 (positive everywhere), -1 (a value <= 0 was
+// found at a vertex of a piece) or 0 (undecided after `budget` pieces).
+int bernstein_sign(const double* coef, int m, int budget) {
+  auto mi = mi3_list(m);
+  const int np = (int)mi.size();
+  if (m == 0) return coef[0] > 0 ? 1 : -1;
+  // position of a multi-index given (a1, a2, a3) through a dense lookup
+  std::vector<int> pos((size_t)(m + 1) * (m + 1) * (m + 1), -1);
+  for (int i = 0; i < np; ++i) pos[((size_t)mi[i][1] * (m + 1) + mi[i][2]) * (m + 1) + mi[i][3]] = i;
+  auto at = [&](int a1, int a2, int a3) { return pos[((size_t)a1 * (m + 1) + a2) * (m + 1) + a3]; };
+  int vtx[4];
+  vtx[0] = at(0, 0, 0), vtx[1] = at(m, 0, 0), vtx[2] = at(0, m, 0), vtx[3] = at(0, 0, m);
+  struct Piece {
+    std::vector<double> c;
+    double v[4][4];  // barycentric coordinates (original element) of the piece's vertices
+  };
+  std::vector<Piece> stack;
+  Piece root;
+  root.c.assign(coef, coef + np);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) root.v[i][j] = i == j ? 1.0 : 0.0;
+  stack.push_back(std::move(root));
+  int used = 0;
+  std::vector<double> line((size_t)m + 1), left((size_t)m + 1), right((size_t)m + 1);
+  while (!stack.empty()) {
+    Piece p = std::move(stack.back());
+    stack.pop_back();
+    for (int i = 0; i < 4; ++i)
+      if (!(p.c[vtx[i]] > 0)) return -1;
+    double lo = p.c[0];
+    for (int i = 1; i < np; ++i) lo = std::min(lo, p.c[i]);
+    if (lo > 0) continue;
+    if (++used > budget) return 0;
+    // longest edge of the piece
+    int ei = 0, ej = 1;
+    double best = -1;
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j) {
+        double d = 0;
+        for (int t = 0; t < 4; ++t) d += (p.v[i][t] - p.v[j][t]) * (p.v[i][t] - p.v[j][t]);
+        if (d > best) best = d, ei = i, ej = j;
+      }
+    Piece A, B;
+    A.c.assign(np, 0.0), B.c.assign(np, 0.0);
+    std::memcpy(A.v, p.v, sizeof p.v), std::memcpy(B.v, p.v, sizeof p.v);
+    for (int t = 0; t < 4; ++t) A.v[ej][t] = B.v[ei][t] = 0.5 * (p.v[ei][t] + p.v[ej][t]);
+    // every line of coefficients with the other two indices fixed is a univariate
+    // Bernstein polynomial in (lambda_ei, lambda_ej) of degree a_ei + a_ej
+    for (int i = 0; i < np; ++i) {
+      std::array<int, 4> a = mi[i];
+      if (a[ej] != 0) continue;  // visit each line once, from its a_ej = 0 end
+      const int len = a[ei];
+      for (int k = 0; k <= len; ++k) {
+        std::array<int, 4> b = a;
+        b[ei] = len - k, b[ej] = k;
+        line[k] = p.c[at(b[1], b[2], b[3])];
+      }
+      // de Casteljau at 1/2: left piece (ej moved to the midpoint) takes the first entry of
+      // each level, right piece (ei moved) the last
+      for (int r = 0; r <= len; ++r) {
+        left[r] = line[0];
+        right[len - r] = line[len - r];
+        for (int k = 0; k < len - r; ++k) line[k] = 0.5 * (line[k] + line[k + 1]);
+      }
+      for (int k = 0; k <= len; ++k) {
+        std::array<int, 4> b = a;
+        b[ei] = len - k, b[ej] = k;
+        const int q = at(b[1], b[2], b[3]);
+        A.c[q] = left[k];
+        B.c[q] = right[k];
+      }
+    }
+    stack.push_back(std::move(A));
+    stack.push_back(std::move(B));
+  }
+  return 1;
+}
+
 // ------------------------------------------------------------- projection coefficients
 // Distinct eigenvalue k of the degree-n Bernstein mass matrix of the volume-4/3
 // reference tetrahedron: (4/3) 3! (n!)^2 / ((n-k)! (n+k+3)!).
 ld mass_eig(int n, int k) { return 8.0L * factl(n) * factl(n) / (factl(n - k) * factl(n + k + 3)); }
 
-// c_j of the telescoped projection (paper Theorem 5.1). In the orthogonal modal basis
+// c_j of the telescoped projection (paper Theorem 5.3). In the orthogonal modal basis
 // E^N_{N-j}(E^N_{N-j})^T is diagonal with entries lambda^{N-j}_k / lambda^N_k on modes of
 // degree k <= N-j (paper Corollary A.3) and the reduction (E^{N+M}_N)^T scales mode k by
 // lambda^N_k / lambda^{N+M}_k (Lemma A.2), so requiring the identity on P^N gives the
 // triangular system sum_{j=0}^{N-k} c_j lambda^{N-j}_k = lambda^{N+M}_k, k = N..0.
-// With M < 0 the right-hand side is 1 (inverse mass matrix, Theorem 5.2).
+// With M < 0 the right-hand side is 1 (inverse mass matrix, Theorem 5.5).
 void projection_cj(int N, int M, ld* c) {
   for (int k = N; k >= 0; --k) {
     int jn = N - k;
@@ -273,6 +358,8 @@ struct bbwadg_ctx {
   std::vector<int32_t> conn;     // [K][4]
   std::vector<double> c2;        // [K][Mp]
   bool c2_set = false, c2_dirty = false;
+  int c2_policy = BBWADG_C2_REQUIRE_POSITIVE;
+  int64_t c2_nonpositive = 0, c2_undecided = 0;  // of the stored c^2_M
   HostTables tables;
   Projector proj[kMaxN + 1];
   // device
@@ -372,20 +459,54 @@ int dmalloc(void** p, size_t bytes) {
   return e == hipSuccess ? 0 : fail(BBWADG_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
 }
 
-// c^2_M must be finite and positive at the points of the degree-M projection rule.
-int check_c2(const bbwadg_ctx* ctx, const double* coef, int64_t k0, int64_t k1) {
-  const Projector& pr = get_projector(ctx, ctx->M);
-  int mp = ctx->Mp;
-  for (int64_t k = k0; k < k1; ++k) {
-    const double* c = coef + (k - k0) * mp;
-    for (int i = 0; i < mp; ++i)
-      if (!std::isfinite(c[i])) return fail(BBWADG_EC2, "c^2 coefficient of element %lld not finite", (long long)k);
-    for (int q = 0; q < pr.nq; ++q) {
-      double v = 0;
-      for (int i = 0; i < mp; ++i) v += pr.B[(size_t)q * mp + i] * c[i];
-      if (!(v > 0)) return fail(BBWADG_EC2, "c^2_M <= 0 in element %lld", (long long)k);
+// Classification of n sets of degree-m Bernstein coefficients [n][dimp(m)]: counts of sets
+// that are not positive everywhere on their element (a value <= 0 found) and of sets whose
+// sign the subdivision budget could not decide. EC2 if a coefficient is not finite.
+struct PositivityCount {
+  int64_t nonpositive = 0, undecided = 0, first = -1;
+};
+constexpr int kSignBudget = 4096;  // pieces per element before a set counts as undecided
+
+int classify_positive(const double* coef, int m, int64_t n, PositivityCount& out, const char* what) {
+  const int mp = dimp(m);
+  for (int64_t i = 0; i < n * mp; ++i)
+    if (!std::isfinite(coef[i]))
+      return fail(BBWADG_EC2, "%s coefficient of element %lld not finite", what, (long long)(i / mp));
+  std::atomic<int64_t> nonpos{0}, undec{0}, first{std::numeric_limits<int64_t>::max()};
+  parallel_for(0, n, [&](int64_t a, int64_t b) {
+    int64_t np_ = 0, ud = 0, f = std::numeric_limits<int64_t>::max();
+    for (int64_t k = a; k < b; ++k) {
+      const int sg = bernstein_sign(coef + k * mp, m, kSignBudget);
+      if (sg < 0) ++np_;
+      if (sg == 0) ++ud;
+      if (sg <= 0 && k < f) f = k;
     }
-  }
+    nonpos += np_;
+    undec += ud;
+    int64_t cur = first.load();
+    while (f < cur && !first.compare_exchange_weak(cur, f)) {
+    }
+  });
+  out.nonpositive = nonpos.load();
+  out.undecided = undec.load();
+  out.first = out.nonpositive + out.undecided > 0 ? first.load() : -1;
+  return 0;
+}
+
+// c^2_M must be finite, and positive everywhere on every element (the weight of the
+// weight-adjusted mass matrix, Section 3) unless the context's policy accepts otherwise.
+int check_c2(bbwadg_ctx* ctx, const double* coef) {
+  PositivityCount pc;
+  int rc = classify_positive(coef, ctx->M, ctx->K, pc, "c^2");
+  if (rc) return rc;
+  if (ctx->c2_policy == BBWADG_C2_REQUIRE_POSITIVE && pc.nonpositive + pc.undecided > 0)
+    return fail(BBWADG_EC2,
+                "c^2_M is not positive everywhere on %lld elements (%lld with a value <= 0, %lld undecided; "
+                "first element %lld)",
+                (long long)(pc.nonpositive + pc.undecided), (long long)pc.nonpositive, (long long)pc.undecided,
+                (long long)pc.first);
+  ctx->c2_nonpositive = pc.nonpositive;
+  ctx->c2_undecided = pc.undecided;
   return 0;
 }
 
@@ -853,11 +974,39 @@ int bbwadg_project_samples(const bbwadg_ctx* c, int32_t degree, int64_t k0, int6
 
 int bbwadg_set_c2(bbwadg_ctx* c, const double* coef) {
   if (!c || !coef) return fail(BBWADG_EINVAL, "NULL argument");
-  int rc = check_c2(c, coef, 0, c->K);
+  int rc = check_c2(c, coef);
   if (rc) return rc;
   c->c2.assign(coef, coef + (size_t)c->K * c->Mp);
   c->c2_set = true;
   c->c2_dirty = true;
+  return 0;
+}
+
+int bbwadg_set_c2_policy(bbwadg_ctx* c, int32_t policy) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (policy != BBWADG_C2_REQUIRE_POSITIVE && policy != BBWADG_C2_ACCEPT_NONPOSITIVE)
+    return fail(BBWADG_EINVAL, "unknown c^2 policy %d", (int)policy);
+  c->c2_policy = policy;
+  return 0;
+}
+
+int bbwadg_c2_positivity(const bbwadg_ctx* c, int64_t* n_nonpositive, int64_t* n_undecided) {
+  if (!c) return fail(BBWADG_EINVAL, "NULL context");
+  if (!c->c2_set) return fail(BBWADG_EC2, "c^2 not set");
+  if (n_nonpositive) *n_nonpositive = c->c2_nonpositive;
+  if (n_undecided) *n_undecided = c->c2_undecided;
+  return 0;
+}
+
+int bbwadg_bernstein_positivity(int32_t degree, int64_t n, const double* coef, int64_t* n_nonpositive,
+                                int64_t* n_undecided, int64_t* first) {
+  if (degree < 0 || degree > kMaxDeg || n < 0 || (n > 0 && !coef)) return fail(BBWADG_EINVAL, "bad argument");
+  PositivityCount pc;
+  int rc = classify_positive(coef, degree, n, pc, "Bernstein");
+  if (rc) return rc;
+  if (n_nonpositive) *n_nonpositive = pc.nonpositive;
+  if (n_undecided) *n_undecided = pc.undecided;
+  if (first) *first = pc.first;
   return 0;
 }
 
@@ -1657,19 +1806,43 @@ int bbwadg_elastic_set_media(bbwadg_ctx* c, const double* rho_inv, const double*
   if (!rho_inv || !lam || !mu) return fail(BBWADG_EINVAL, "NULL medium array");
   const size_t n = (size_t)c->K * c->Mp;
   const double* src[3] = {rho_inv, lam, mu};
-  void** dst[3] = {&c->d_el_rho, &c->d_el_lam, &c->d_el_mu};
-  for (int f = 0; f < 3; ++f)
-    for (size_t i = 0; i < n; ++i)
-      if (!std::isfinite(src[f][i])) return fail(BBWADG_EINVAL, "medium %d coefficient %zu not finite", f, i);
+  // The weights of the velocity-stress mass matrices must be positive everywhere: 1/rho,
+  // mu and the bulk term 3 lambda + 2 mu (a degree-M polynomial with coefficients
+  // 3 lambda_b + 2 mu_b). Everything is checked before anything is uploaded.
+  std::vector<double> bulk(n);
+  for (size_t i = 0; i < n; ++i) bulk[i] = 3.0 * lam[i] + 2.0 * mu[i];
+  const double* chk[3] = {rho_inv, mu, bulk.data()};
+  const char* names[3] = {"1/rho", "mu", "3 lambda + 2 mu"};
   for (int f = 0; f < 3; ++f) {
-    if (!*dst[f] && (rc = dmalloc(dst[f], n * c->rsz))) return rc;
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(src[f][i])) return fail(BBWADG_EC2, "medium %d coefficient %zu not finite", f, i);
+    PositivityCount pc;
+    if ((rc = classify_positive(chk[f], c->M, c->K, pc, names[f]))) return rc;
+    if (c->c2_policy == BBWADG_C2_REQUIRE_POSITIVE && pc.nonpositive + pc.undecided > 0)
+      return fail(BBWADG_EC2, "%s is not positive everywhere on %lld elements (first element %lld)", names[f],
+                  (long long)(pc.nonpositive + pc.undecided), (long long)pc.first);
+  }
+  // upload into fresh buffers, then replace the old ones: a failure leaves the old media
+  void* fresh[3] = {nullptr, nullptr, nullptr};
+  for (int f = 0; f < 3 && !rc; ++f) {
+    rc = dmalloc(&fresh[f], n * c->rsz);
+    if (rc) break;
     if (c->dtype == BBWADG_F64) {
-      rc = upload(*dst[f], src[f], n * 8);
+      rc = upload(fresh[f], src[f], n * 8);
     } else {
       std::vector<float> v(src[f], src[f] + n);
-      rc = upload(*dst[f], v.data(), n * 4);
+      rc = upload(fresh[f], v.data(), n * 4);
     }
-    if (rc) return rc;
+  }
+  if (rc) {
+    for (void* p : fresh)
+      if (p) (void)hipFree(p);
+    return rc;
+  }
+  void** dst[3] = {&c->d_el_rho, &c->d_el_lam, &c->d_el_mu};
+  for (int f = 0; f < 3; ++f) {
+    if (*dst[f]) (void)hipFree(*dst[f]);
+    *dst[f] = fresh[f];
   }
   return 0;
 }

@@ -7,7 +7,7 @@
 //             face, so traces are coefficient-wise), lift L^f = E_L L_0 with
 //             L_0 = (2N+3)/2 I + N^2/2 E E^T and layer i scaled by l_i (Section 4);
 //   WADG    : product with c^2_M (eq. mcoeff), M one-degree reductions and the telescoped
-//             projection (eq. telescope) with the c_j of Theorem 5.1 (Section 5);
+//             projection (eq. telescope) with the c_j of Theorem 5.3 (Section 5);
 //   update  : res = a res + dt rhs, q_out = q_in + b res (low-storage RK4 stage).
 //
 // Design for CDNA4:

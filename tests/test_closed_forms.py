@@ -37,7 +37,7 @@ def mass_eigenvalue(n, k):
 
 
 def projection_cj(N, M, mass_inverse=False):
-    """c_j of Theorem 5.1 (or of the mass-inverse representation): in the modal basis the
+    """c_j of Theorem 5.3 (or of the mass-inverse representation): in the modal basis the
     elevation products are diagonal (Corollary A.3), which gives the triangular system
     sum_{j<=N-k} c_j lambda^{N-j}_k = lambda^{N+M}_k (or 1), k = N..0."""
     c = []
@@ -175,7 +175,7 @@ def test_conditioning_sums():
 
 @pytest.mark.parametrize("N,M", [(1, 1), (2, 1), (3, 1), (3, 2), (4, 2), (5, 2), (6, 3)])
 def test_telescoped_projection_equals_dense_l2_projection(N, M):
-    """Theorem 5.1: sum_j c_j E^N_{N-j} (E^N_{N-j})^T (E^{N+M}_N)^T is the L^2 projection
+    """Theorem 5.3: sum_j c_j E^N_{N-j} (E^N_{N-j})^T (E^{N+M}_N)^T is the L^2 projection
     M_N^{-1} (E^{N+M}_N)^T M_{N+M} (mass matrices from exact quadrature)."""
     r, s, t, w = tet_rule(N + M + 1)
     BN = bernstein_tet(N, r, s, t)

@@ -1,7 +1,7 @@
 """The dense quadrature WADG baseline (matrix-core kernel) through the C ABI.
 
 * With c^2_M at the dense points it must equal the fast Bernstein right-hand side (the
-  projection is exact for that rule: paper Theorem 5.1 against eq. pwadg).
+  projection is exact for that rule: paper Theorem 5.3 against eq. pwadg).
 * With the true c^2 at the points it must equal the oracle's plain WADG mode (c^2 point
   values at the same collapsed rule, dense quadrature matrices in an orthonormal basis).
 Tolerance 1e-11 relative L2 per field (FP64); sizes span several 16-element tiles and a

@@ -85,10 +85,24 @@ def test_elastic_error_paths(bb):
     assert ei.value.code == -3
     bad = np.ones((s.K, s.Mp))
     bad[0, 0] = np.inf
-    with pytest.raises(bb.BBWADGError):
-        s.elastic_set_media(bad, bad * 0 + 1, bad * 0 + 1)
+    with pytest.raises(bb.BBWADGError) as ei:
+        s.elastic_set_media(bad, np.ones_like(bad), np.ones_like(bad))
+    assert ei.value.code == -3
     with pytest.raises(ValueError):
         s.elastic_update(torch.zeros((4, s.K, s.Np), dtype=torch.float64, device="cuda"))
+    # valid media, then media that are not positive: the weights 1/rho, mu and 3 lambda + 2 mu
+    # must be positive everywhere; a rejected call leaves the previous media in place
+    one = np.ones((s.K, s.Mp))
+    s.elastic_set_media(one, one, one)
+    rr = torch.as_tensor(np.random.default_rng(5).standard_normal((9, s.K, s.Np)), device="cuda")
+    before = s.elastic_update(rr).cpu()
+    for rho_inv, lam, mu in [(-one, one, one), (one, one, -0.5 * one), (one, -one, one)]:
+        with pytest.raises(bb.BBWADGError) as ei:
+            s.elastic_set_media(rho_inv, lam, mu)
+        assert ei.value.code == -3
+    assert torch.equal(s.elastic_update(rr).cpu(), before)
+    s.set_c2_policy(True)  # the accepting policy stores them
+    s.elastic_set_media(one, -one, one)
 
 
 @pytest.mark.parametrize("N,M", [(1, 0), (2, 1), (3, 3), (5, 2), (7, 3), (9, 4)])

@@ -283,7 +283,13 @@ def test_layered_medium_step_parity(bb, N, dtype):
     pulse = lambda x, y, z: ic_gaussian_pulse(x, y, z, width=0.2)  # noqa: E731
     zero = lambda x, y, z: 0.0 * x  # noqa: E731
     s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    # The projected jumps dip below zero inside some elements: rejected by default, accepted
+    # here on purpose (parity of the arithmetic holds for any weight; 3 steps stay bounded).
+    with pytest.raises(bb.BBWADGError):
+        s.project_c2(medium)
+    s.set_c2_policy(True)
     s.project_c2(medium)
+    assert s.c2_positivity()[0] > 0
     q = s.to_device(s.initial_state([pulse, zero, zero, zero]))
     res = torch.zeros_like(q)
     dt = 5e-4
