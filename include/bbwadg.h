@@ -237,11 +237,12 @@ int bbwadg_project_fn(bbwadg_ctx* ctx, double (*fn)(double x, double y, double z
 /* ---- dense quadrature WADG: the comparison baseline (paper Section 3.3, eq. pwadg) ----
  * dp/dt = P_q diag(c^2(x_q)) V_q r_p with V_q the degree-N Bernstein basis at the points of
  * the collapsed Gauss-Jacobi rule with n = floor((2N+M+2)/2) points per direction (exact to
- * degree 2N+M) and P_q = M^{-1} V_q^T W, applied as dense products on the FP64 matrix cores.
- * With c^2_M at the points it equals the fast Bernstein update (paper Theorem 5.3); with the
- * true c^2 at the points it is the quadrature WADG the paper compares against. FP64 device
- * contexts only (EINVAL otherwise). The point values take K * 16 ceil(nq/16) doubles of
- * device memory, allocated by the first bbwadg_dense_set_c2 together with the tables. */
+ * degree 2N+M) and P_q = M^{-1} V_q^T W, applied as dense products on the matrix cores in
+ * the context's precision (FP64, or FP32 with FP32 accumulation). With c^2_M at the points it
+ * equals the fast Bernstein update (paper Theorem 5.3); with the true c^2 at the points it is
+ * the quadrature WADG the paper compares against. Device contexts only. The point values take
+ * K * 16 ceil(nq/16) reals of device memory, allocated by the first bbwadg_dense_set_c2
+ * together with the tables. */
 
 /* Points of the dense rule per element (nq = n^3). */
 int bbwadg_dense_npoints(const bbwadg_ctx* ctx, int64_t* nq);
@@ -255,12 +256,14 @@ int bbwadg_dense_points(const bbwadg_ctx* ctx, int64_t k0, int64_t k1, double* x
 int bbwadg_dense_set_c2(bbwadg_ctx* ctx, const double* c2q, void* stream);
 
 /* The dense update alone: out[k] = P_q diag(c^2 at element k's points) V_q r[k] for device
- * FP64 arrays r, out [K][Np] (they may be the same array). EC2 before bbwadg_dense_set_c2. */
+ * arrays r, out [K][Np] of the context dtype (they may be the same array). EC2 before
+ * bbwadg_dense_set_c2. */
 int bbwadg_dense_update(bbwadg_ctx* ctx, const void* r, void* out, void* stream);
 
 /* Right-hand side with the dense update in place of the Bernstein one: the plain DG
  * right-hand side (volume, fluxes and lift as in bbwadg_rhs, with c^2 = 1) followed by
- * bbwadg_dense_update on the p field. q, rhs: device [4][K][Np] FP64, must not overlap. */
+ * bbwadg_dense_update on the p field. q, rhs: device [4][K][Np] of the context dtype, must
+ * not overlap. */
 int bbwadg_rhs_dense(bbwadg_ctx* ctx, const void* q, void* rhs, double t, void* stream);
 
 /* ---- receivers, misfit and its gradient with respect to c^2_M -------------------------

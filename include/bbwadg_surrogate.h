@@ -57,6 +57,13 @@ int bbwadg_sur_forward(bbwadg_sur* s, const float* x, int32_t B, float* y, void*
 int bbwadg_sur_loss_grad(bbwadg_sur* s, const float* x, const float* t, int32_t B, double* loss, float* grad_host,
                          void* stream);
 
+/* The loss of bbwadg_sur_loss_grad (*loss, host) and its gradient with respect to the input,
+ * dL/dx into dx (device FP32 [B][16][16][16], the layout of x): the network as a
+ * differentiable stand-in for the forward solve (the parameter gradient is formed as well and
+ * kept in the context). Synchronises `stream`. */
+int bbwadg_sur_input_grad(bbwadg_sur* s, const float* x, const float* t, int32_t B, double* loss, float* dx,
+                          void* stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the gradient of
  * bbwadg_sur_loss_grad at (x, t); *loss gets the loss before the step. */
 int bbwadg_sur_train_step(bbwadg_sur* s, const float* x, const float* t, int32_t B, float lr, double* loss, void* stream);

@@ -6,7 +6,8 @@ parameters are read from the library's flat vector with its documented layout (W
 row-major, convolution row ((kz*3 + ky)*3 + kx)*Cin + c, then the bias). The inputs of every
 product (the input grid, the weights and each layer's output) are rounded to BF16 as the
 library's matrix-core GEMMs take them; the products and sums are FP32. Gradients come from
-torch autograd on this definition (without rounding the backward pass).
+torch autograd on this definition (without rounding the backward pass); the gradient with
+respect to the input takes the input's BF16 rounding as the identity, as the library does.
 """
 from __future__ import annotations
 
@@ -65,3 +66,13 @@ class SurrogateNet:
         loss = torch.mean((y - t) ** 2)
         loss.backward()
         return float(loss.detach()), p.grad.detach().numpy(), y.detach().numpy()
+
+    def input_grad(self, p_np, x_np, t_np, rounding: bool = True, dtype=torch.float32):
+        """(loss, dL/dx) of the mean squared error by autograd."""
+        p = torch.tensor(np.asarray(p_np), dtype=dtype)
+        x = torch.tensor(np.asarray(x_np), dtype=dtype, requires_grad=True)
+        t = torch.tensor(np.asarray(t_np), dtype=dtype)
+        y = self.forward(p, x, rounding)
+        loss = torch.mean((y - t) ** 2)
+        loss.backward()
+        return float(loss.detach()), x.grad.detach().numpy()

@@ -35,7 +35,7 @@ EXPORTS = (
     "bbwadg_wadg_update", "bbwadg_set_c2_policy", "bbwadg_c2_positivity", "bbwadg_bernstein_positivity",
     "bbwadg_sur_create", "bbwadg_sur_destroy", "bbwadg_sur_num_params", "bbwadg_sur_layout",
     "bbwadg_sur_get_params", "bbwadg_sur_set_params", "bbwadg_sur_forward", "bbwadg_sur_loss_grad",
-    "bbwadg_sur_train_step",
+    "bbwadg_sur_train_step", "bbwadg_sur_input_grad",
     "bbwadg_projection_coefficients", "bbwadg_version",
 )
 
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_sur_forward": (C.c_int, [vp, vp, i32, vp, vp]),
         "bbwadg_sur_loss_grad": (C.c_int, [vp, vp, vp, i32, pd, vp, vp]),
         "bbwadg_sur_train_step": (C.c_int, [vp, vp, vp, i32, C.c_float, pd, vp]),
+        "bbwadg_sur_input_grad": (C.c_int, [vp, vp, vp, i32, pd, vp, vp]),
         "bbwadg_projection_coefficients": (C.c_int, [i32, i32, pd]),
         "bbwadg_version": (C.c_char_p, []),
     }
@@ -576,13 +577,14 @@ class Solver:
         _check(self._lib.bbwadg_dense_set_c2(self._ctx, C.c_void_p(vals.ctypes.data), self._stream()))
 
     def dense_update(self, r, out=None):
-        """out[k] = P_q diag(c^2) V_q r[k] for device float64 arrays of shape (K, Np)."""
+        """out[k] = P_q diag(c^2) V_q r[k] for device arrays of shape (K, Np) of the context dtype."""
         import torch
+        want = torch.float64 if self.dtype == "f64" else torch.float32
         if out is None:
             out = torch.empty_like(r)
         for t, name in ((r, "r"), (out, "out")):
-            if not (t.is_cuda and t.dtype == torch.float64 and tuple(t.shape) == (self.K, self.Np) and t.is_contiguous()):
-                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape ({self.K}, {self.Np})")
+            if not (t.is_cuda and t.dtype == want and tuple(t.shape) == (self.K, self.Np) and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {want} device tensor of shape ({self.K}, {self.Np})")
         _check(self._lib.bbwadg_dense_update(self._ctx, C.c_void_p(r.data_ptr()), C.c_void_p(out.data_ptr()),
                                              self._stream()))
         return out

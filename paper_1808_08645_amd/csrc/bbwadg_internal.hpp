@@ -15,6 +15,27 @@ constexpr int kMaxDeg = kMaxN + kMaxM;
 __host__ __device__ constexpr int dimp(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
 __host__ __device__ constexpr int dim2(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) / 2; }
 
+// Error-free transformations of float arithmetic (Knuth's two-sum; the FMA product
+// error): s + e == a + b and p + e == a b exactly. Contraction is switched off so that the
+// sums are the rounded sums the formulas assume.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+
+// Smallest degree whose FP32 kernels run the telescoped projection in float pairs.
+#ifndef BBW_COMP_MIN_N
+#define BBW_COMP_MIN_N 8
+#endif
+
 // Per-element geometry record: G[9] (G[3i+j] = d r_j / d x_i), then for each face f:
 // Fscale_f, n_f (3 values).
 constexpr int kGeoStride = 25;
@@ -35,6 +56,8 @@ struct StageArgs {
   real src_amp;           // s(t) of the source f = s(t) g(x) at this stage's time
   real* rp_out;           // [K][Np] r_p before the weight adjustment (source included), or null (step mode)
   real cj[kMaxN + 1];     // telescoped projection coefficients c_j
+  // c_j ((N-j)!)^2 / N! as a pair hi + lo of reals (the compensated FP32 telescoping)
+  real cjx_hi[kMaxN + 1], cjx_lo[kMaxN + 1];
 };
 
 // Launch one fused stage (UPDATE) or one right-hand-side evaluation on `stream`.
@@ -63,21 +86,24 @@ struct QuadReduceArgs {
 };
 int quad_reduce_blocks(int64_t nelems, int max_blocks);
 
-// Dense quadrature WADG update out = P_q diag(c2q) V_q r (FP64), tables in MFMA operand order:
+// Dense quadrature WADG update out = P_q diag(c2q) V_q r (FP64 or FP32), tables in MFMA
+// operand order:
 // va[qc][ks][lane] = V_q[16 qc + lane%16][4 ks + lane/16] (NQP/16 x NPP/4 x 64) and
 // pa[qc][t][ks][lane] = P_q[16 t + lane%16][16 qc + 4 ks + lane/16] (NQP/16 x NPP/16 x 4 x 64),
 // zero-padded to NPP = 16 ceil(Np/16) and NQP = 16 ceil(Nq/16).
+template <typename real>
 struct DenseArgs {
-  const double* r;    // [K][Np] input coefficients
-  double* out;        // [K][Np] result (may alias r: each tile stages its inputs first)
-  const double* va;
-  const double* pa;
-  const double* c2q;  // [K][nqp] c^2 at the points (padding zero)
+  const real* r;    // [K][Np] input coefficients
+  real* out;        // [K][Np] result (may alias r: each tile stages its inputs first)
+  const real* va;
+  const real* pa;
+  const real* c2q;  // [K][nqp] c^2 at the points (padding zero)
   int64_t K;
-  int32_t nqc;        // NQP / 16
-  int32_t nqp;        // NQP
+  int32_t nqc;      // NQP / 16
+  int32_t nqp;      // NQP
 };
-int launch_wadg_dense(int N, const DenseArgs& a, void* stream);
+template <typename real>
+int launch_wadg_dense(int N, const DenseArgs<real>& a, void* stream);
 
 // Weight-adjusted update of the 9 elastic fields (elastic_kernel.hip): r, out [9][K][Np]
 // (v1, v2, v3, sigma xx, yy, zz, yz, xz, xy); weights [K][Mp] as Bernstein coefficients.
@@ -90,6 +116,7 @@ struct ElasticArgs {
   const real* mu;
   int64_t K;
   real cj[kMaxN + 1];
+  real cjx_hi[kMaxN + 1], cjx_lo[kMaxN + 1];  // as in StageArgs
   // optional low-storage RK stage in place of out (res != nullptr): res = rk_a res + dt u,
   // q += rk_b res, u the update of r; res, q [9][K][Np]
   real* res;

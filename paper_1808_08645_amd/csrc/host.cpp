@@ -13,6 +13,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bbwadg.h"
@@ -382,10 +383,12 @@ struct bbwadg_ctx {
   // dense quadrature WADG (comparison baseline)
   Projector dense;              // degree N at the dense rule: B = V_q, P = P_q
   int dense_n = 0, dense_nqp = 0;
-  void* d_dva = nullptr;        // V_q in MFMA operand order
-  void* d_dpa = nullptr;        // P_q in MFMA operand order
+  void* d_dva = nullptr;        // V_q in MFMA operand order (FP64; also the adjoint's)
+  void* d_dpa = nullptr;        // P_q in MFMA operand order (FP64)
+  void* d_dva32 = nullptr;      // the same tables in FP32 (FP32 contexts)
+  void* d_dpa32 = nullptr;
   void* d_c2q = nullptr;        // [K][dense_nqp] c^2 at the dense points
-  void* d_ones = nullptr;       // [K] ones: c^2 = 1 for the plain DG right-hand side
+  void* d_ones = nullptr;       // [K] ones of the context dtype: c^2 = 1 for the plain DG right-hand side
   bool c2q_set = false;
   // pressure source f(x, t) = amp sin(omega t + phase) g(x)
   void* d_src = nullptr;        // [K][Np] coefficients of g (dtype)
@@ -435,7 +438,7 @@ const Projector& get_projector(const bbwadg_ctx* ctx, int d) {
 void free_device(bbwadg_ctx* c) {
   void** ptrs[] = {&c->d_geo,     &c->d_conn,    &c->d_c2,         &c->d_c2k, &c->d_q2,
                    &c->d_J,       &c->d_mass,    &c->d_partial,    &c->d_rbasis, &c->d_rbasis_c2,
-                   &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones,
+                   &c->d_rw,      &c->d_dva,     &c->d_dpa,        &c->d_c2q, &c->d_ones, &c->d_dva32, &c->d_dpa32,
                    &c->d_src,     &c->d_rec_elem, &c->d_rec_basis, &c->d_rec_kvec, &c->d_adj_bwa,
                    &c->d_adj_ones, &c->d_el_rho, &c->d_el_lam, &c->d_el_mu, &c->d_el_fpos, &c->d_el_tmp, &c->d_el_rhs};
   for (void** p : ptrs) {
@@ -538,6 +541,26 @@ int sync_c2(bbwadg_ctx* ctx, hipStream_t s) {
   return 0;
 }
 
+// The c_j of the telescoped projection for a kernel's argument block, and the pairs
+// hi + lo = c_j ((N-j)!)^2 / N! of the compensated FP32 telescoping (unnormalised sweeps).
+template <typename Args>
+void set_cj(const bbwadg_ctx* c, Args& a) {
+  using real = std::remove_reference_t<decltype(a.cj[0])>;
+  ld fn = 1;
+  for (int i = 2; i <= c->N; ++i) fn *= i;
+  for (int j = 0; j <= kMaxN; ++j) {
+    a.cj[j] = (real)c->tables.cj[j];
+    ld v = 0;
+    if (j <= c->N) {
+      ld f = 1;
+      for (int i = 2; i <= c->N - j; ++i) f *= i;
+      v = (ld)c->tables.cj[j] * f * f / fn;
+    }
+    a.cjx_hi[j] = (real)v;
+    a.cjx_lo[j] = (real)(v - (ld)a.cjx_hi[j]);
+  }
+}
+
 template <typename real>
 StageArgs<real> make_args(const bbwadg_ctx* c) {
   StageArgs<real> a{};
@@ -548,7 +571,7 @@ StageArgs<real> make_args(const bbwadg_ctx* c) {
   a.tau_p = (real)c->tau_p;
   a.tau_u = (real)c->tau_u;
   a.bc = c->bc;
-  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  set_cj(c, a);
   a.src = (const real*)c->d_src;
   a.src_amp = real(0);
   a.rp_out = nullptr;
@@ -678,14 +701,23 @@ int dense_tables(bbwadg_ctx* c) {
         }
     }
   std::vector<double> ones((size_t)c->K, 1.0);
+  const bool f32 = c->dtype == BBWADG_F32;
   int rc = dmalloc(&c->d_dva, va.size() * 8);
   if (!rc) rc = dmalloc(&c->d_dpa, pa.size() * 8);
-  if (!rc) rc = dmalloc(&c->d_ones, ones.size() * 8);
+  if (!rc) rc = dmalloc(&c->d_ones, ones.size() * c->rsz);
   if (!rc) rc = upload(c->d_dva, va.data(), va.size() * 8);
   if (!rc) rc = upload(c->d_dpa, pa.data(), pa.size() * 8);
-  if (!rc) rc = upload(c->d_ones, ones.data(), ones.size() * 8);
+  if (!rc && !f32) rc = upload(c->d_ones, ones.data(), ones.size() * 8);
+  if (!rc && f32) {
+    std::vector<float> va32 = convert<float>(va), pa32 = convert<float>(pa), ones32 = convert<float>(ones);
+    rc = dmalloc(&c->d_dva32, va32.size() * 4);
+    if (!rc) rc = dmalloc(&c->d_dpa32, pa32.size() * 4);
+    if (!rc) rc = upload(c->d_dva32, va32.data(), va32.size() * 4);
+    if (!rc) rc = upload(c->d_dpa32, pa32.data(), pa32.size() * 4);
+    if (!rc) rc = upload(c->d_ones, ones32.data(), ones32.size() * 4);
+  }
   if (rc) {
-    void** ptrs[] = {&c->d_dva, &c->d_dpa, &c->d_ones};
+    void** ptrs[] = {&c->d_dva, &c->d_dpa, &c->d_ones, &c->d_dva32, &c->d_dpa32};
     for (void** p : ptrs) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
@@ -1195,7 +1227,6 @@ int bbwadg_dense_points(const bbwadg_ctx* ctx, int64_t k0, int64_t k1, double* x
 int bbwadg_dense_set_c2(bbwadg_ctx* c, const double* c2q, void* stream) {
   int rc = require_device(c);
   if (rc) return rc;
-  if (c->dtype != BBWADG_F64) return fail(BBWADG_EINVAL, "the dense WADG baseline runs in FP64 contexts only");
   if (!c2q && !c->c2_set) return fail(BBWADG_EC2, "c^2 not set (pass point values or set c^2_M first)");
   if ((rc = dense_tables(c))) return rc;
   const Projector& pr = c->dense;
@@ -1226,9 +1257,12 @@ int bbwadg_dense_set_c2(bbwadg_ctx* c, const double* c2q, void* stream) {
       }
   });
   if (bad.load()) return fail(BBWADG_EC2, "c^2 at the dense points must be finite and positive");
-  if (!c->d_c2q && (rc = dmalloc(&c->d_c2q, buf.size() * 8))) return rc;
+  if (!c->d_c2q && (rc = dmalloc(&c->d_c2q, buf.size() * c->rsz))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(c->d_c2q, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, s);
+  std::vector<float> buf32;
+  if (c->dtype == BBWADG_F32) buf32 = convert<float>(buf);
+  const void* src = c->dtype == BBWADG_F32 ? (const void*)buf32.data() : (const void*)buf.data();
+  hipError_t e = hipMemcpyAsync(c->d_c2q, src, buf.size() * c->rsz, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // buf is a local buffer
   if (e != hipSuccess) return fail(BBWADG_EHIP, "c^2 point values upload: %s", hipGetErrorString(e));
   c->c2q_set = true;
@@ -1240,16 +1274,30 @@ int bbwadg_dense_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
   if (rc) return rc;
   if (!r || !out) return fail(BBWADG_EINVAL, "NULL argument");
   if (!c->c2q_set) return fail(BBWADG_EC2, "call bbwadg_dense_set_c2 first");
-  DenseArgs a{};
-  a.r = (const double*)r;
-  a.out = (double*)out;
-  a.va = (const double*)c->d_dva;
-  a.pa = (const double*)c->d_dpa;
-  a.c2q = (const double*)c->d_c2q;
-  a.K = c->K;
-  a.nqp = c->dense_nqp;
-  a.nqc = c->dense_nqp / 16;
-  int e = launch_wadg_dense(c->N, a, stream);
+  int e;
+  if (c->dtype == BBWADG_F64) {
+    DenseArgs<double> a{};
+    a.r = (const double*)r;
+    a.out = (double*)out;
+    a.va = (const double*)c->d_dva;
+    a.pa = (const double*)c->d_dpa;
+    a.c2q = (const double*)c->d_c2q;
+    a.K = c->K;
+    a.nqp = c->dense_nqp;
+    a.nqc = c->dense_nqp / 16;
+    e = launch_wadg_dense<double>(c->N, a, stream);
+  } else {
+    DenseArgs<float> a{};
+    a.r = (const float*)r;
+    a.out = (float*)out;
+    a.va = (const float*)c->d_dva32;
+    a.pa = (const float*)c->d_dpa32;
+    a.c2q = (const float*)c->d_c2q;
+    a.K = c->K;
+    a.nqp = c->dense_nqp;
+    a.nqc = c->dense_nqp / 16;
+    e = launch_wadg_dense<float>(c->N, a, stream);
+  }
   if (e) return fail(BBWADG_EHIP, "dense update launch: %s", hipGetErrorString((hipError_t)e));
   return 0;
 }
@@ -1261,12 +1309,22 @@ int bbwadg_rhs_dense(bbwadg_ctx* c, const void* q, void* rhs, double t, void* st
   if (q == rhs) return fail(BBWADG_EINVAL, "q and rhs must not overlap");
   if (!c->c2q_set) return fail(BBWADG_EC2, "call bbwadg_dense_set_c2 first");
   hipStream_t s = (hipStream_t)stream;
-  StageArgs<double> a = make_args<double>(c);  // the plain DG right-hand side: c^2 = 1, M = 0
-  a.c2 = (const double*)c->d_ones;
-  a.src_amp = source_factor(c, t);
-  a.qin = (const double*)q;
-  a.qout = (double*)rhs;
-  int e = launch_stage_f64(c->N, 0, false, a, s);
+  int e;
+  if (c->dtype == BBWADG_F64) {
+    StageArgs<double> a = make_args<double>(c);  // the plain DG right-hand side: c^2 = 1, M = 0
+    a.c2 = (const double*)c->d_ones;
+    a.src_amp = source_factor(c, t);
+    a.qin = (const double*)q;
+    a.qout = (double*)rhs;
+    e = launch_stage_f64(c->N, 0, false, a, s);
+  } else {
+    StageArgs<float> a = make_args<float>(c);
+    a.c2 = (const float*)c->d_ones;
+    a.src_amp = (float)source_factor(c, t);
+    a.qin = (const float*)q;
+    a.qout = (float*)rhs;
+    e = launch_stage_f32(c->N, 0, false, a, s);
+  }
   if (e) return fail(BBWADG_EHIP, "stage launch: %s", hipGetErrorString((hipError_t)e));
   return bbwadg_dense_update(c, rhs, rhs, stream);  // the p field, in place
 }
@@ -1426,7 +1484,7 @@ int wadg_apply(bbwadg_ctx* c, const void* x, void* out, hipStream_t s) {
   a.out = (real*)out;
   a.rho_inv = (const real*)c->d_c2;
   a.K = c->K;
-  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  set_cj(c, a);
   const int e = launch_wadg_update<real>(c->N, c->M, a, s);
   return e ? fail(BBWADG_EHIP, "update launch: %s", hipGetErrorString((hipError_t)e)) : 0;
 }
@@ -1674,7 +1732,7 @@ int elastic_update_typed(bbwadg_ctx* c, const void* r, void* out, void* res, voi
   a.lam = (const real*)c->d_el_lam;
   a.mu = (const real*)c->d_el_mu;
   a.K = c->K;
-  for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (real)c->tables.cj[j];
+  set_cj(c, a);
   a.res = (real*)res;
   a.q = (real*)q;
   a.rk_a = (real)ra;
@@ -1785,7 +1843,7 @@ int bbwadg_wadg_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
     a.out = (double*)out;
     a.rho_inv = (const double*)c->d_c2;
     a.K = c->K;
-    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = c->tables.cj[j];
+    set_cj(c, a);
     e = launch_wadg_update<double>(c->N, c->M, a, s);
   } else {
     ElasticArgs<float> a{};
@@ -1793,7 +1851,7 @@ int bbwadg_wadg_update(bbwadg_ctx* c, const void* r, void* out, void* stream) {
     a.out = (float*)out;
     a.rho_inv = (const float*)c->d_c2;
     a.K = c->K;
-    for (int j = 0; j <= kMaxN; ++j) a.cj[j] = (float)c->tables.cj[j];
+    set_cj(c, a);
     e = launch_wadg_update<float>(c->N, c->M, a, s);
   }
   if (e) return fail(BBWADG_EHIP, "update launch: %s", hipGetErrorString((hipError_t)e));

@@ -126,6 +126,32 @@ constexpr int waves_per_team() {
   return dimp(N) <= 64 ? 1 : (dimp(N) + 63) / 64 > 4 ? 4 : (dimp(N) + 63) / 64;
 }
 
+// How a group's global loads are placed around its phases:
+//   kLoadsEarly : neighbour traces and the next group's state/geometry/c^2 requested at the
+//                 top (registers), the RK register after the flux phase (registers);
+//   kLoadsLate  : neighbour traces requested just before the flux phase, the next group's
+//                 data after it (registers; fewer registers held through the volume phases);
+//   kLoadsLds   : neighbour traces one group ahead and the RK register straight into LDS
+//                 (no registers for them; one-wave teams only), the next group's data after
+//                 the flux phase.
+// The choice per degree and precision is the measured fastest (BBW_LOADS forces one).
+enum { kLoadsEarly = 0, kLoadsLate = 1, kLoadsLds = 2 };
+#ifndef BBW_LOADS
+#define BBW_LOADS -1
+#endif
+// Measured (196,608 tets, M = N/2, ms per stage, early / late / LDS): FP64 N=5 0.467 / 0.489 /
+// 0.481, N=7 1.74 / 1.42, N=8 4.16 / 2.49, N=9 4.58 / 3.46; FP32 within 2% of each other at
+// N <= 4 and early fastest from N = 5 (0.272 / 0.278 / 0.281 at N = 5).
+constexpr int loads_table(int bytes, int N, int TW) {
+  (void)TW;
+  return (bytes == 8 && N >= 7) ? kLoadsLate : kLoadsEarly;
+}
+template <typename real, int N, int TW>
+constexpr int stage_loads() {
+  if (BBW_LOADS >= 0) return (BBW_LOADS == kLoadsLds && TW > 1) ? kLoadsLate : BBW_LOADS;
+  return loads_table((int)sizeof(real), N, TW);
+}
+
 // Product positions are kept in registers when MP * S3 is at most this, else derived per use.
 #ifndef BBW_MUL_REGS_MAX
 #define BBW_MUL_REGS_MAX 40
@@ -144,6 +170,10 @@ struct StageLayout {
   static constexpr int NP = dimp(N), NP1 = dimp(N - 1), NFP = dim2(N), NFP1 = dim2(N - 1);
   static constexpr int NH = dimp(N + M), NH1 = dimp(N + M - 1), MP = dimp(M);
   static constexpr int LEV = lev_off(N, N + 1);
+  // FP32 telescoping in float pairs where the c_j amplify rounding most (N >= BBW_COMP_MIN_N);
+  // the levels then have a second (lo) array
+  static constexpr bool COMP = sizeof(real) == 4 && N >= BBW_COMP_MIN_N && M > 0;
+  static constexpr int LEVA = COMP ? 2 * LEV : LEV;
   static constexpr int PW = 25 + MP;                   // per-element scalars: geometry + c^2
   static constexpr int S3 = cdiv(EW * NH, TL);         // 3D slots (degree <= N+M)
   static constexpr int S3N = cdiv(EW * NP, TL);        // 3D slots covering degree N
@@ -167,19 +197,33 @@ struct StageLayout {
   static constexpr int PLY = EW * NP1;
   static constexpr int SA = cmax(4 * PLY + EW * (NP - NP1), CHP * (NFP + NFP1));
   static constexpr int OFF_B = cdiv(OFF_A + SA, 8) * 8;    // chain [NP*CHP] | H, H1, levels
-  static constexpr int SB = cmax(CHP * NP, EW * (NH + NH1 + LEV) + 4 * EW);  // LEV includes the level guards
+  static constexpr int SB = cmax(CHP * NP, EW * (NH + NH1 + LEVA) + 4 * EW);  // LEV includes the level guards
   static constexpr int OFF_Z = OFF_B + SB;                 // a real that stays zero
   static constexpr int TOTAL = cdiv(OFF_Z + 2, 8) * 8;  // slices stay 8-real aligned
-  static constexpr int BYTES = TOTAL * (int)sizeof(real);
+  // direct-load buffer (dwords per team): the RK register [4][S3N] of the group, each real
+  // as sizeof(real)/4 dwords of TL lanes. One-wave teams only: a multi-wave team's buffer
+  // would cost more occupancy (LDS) than its registers do.
+  static constexpr int LOADS = stage_loads<real, N, TW>();
+  static constexpr bool RS_DMA = LOADS == kLoadsLds;
+  static constexpr int NH2 = (int)sizeof(real) / 4;
+  // ... and, before it, the neighbour traces: [4 fields][NH2 halves] x the rows of the SF flux
+  // slots, a row as wide as its items (the last rounded up to 32 lanes), requested one group
+  // ahead
+  static constexpr int NBLAST = cdiv(4 * EW * NFP - TL * (SF - 1), 32) * 32;  // last row's width
+  static constexpr int NBR = TL * (SF - 1) + NBLAST;                         // one field-half
+  static constexpr int NBW = RS_DMA ? 4 * NH2 * NBR : 0;
+  static constexpr int DBW = RS_DMA ? NBW + 4 * S3N * NH2 * TL : 0;
+  static constexpr int BYTES = TOTAL * (int)sizeof(real) + 4 * DBW;
   // teams per workgroup: single-wave teams share a workgroup (up to 4 within 64 KiB of LDS);
   // a multi-wave team is a workgroup of its own, synchronised by the workgroup barrier
   static constexpr int TPB = TW > 1 ? 1 : cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
   static constexpr int WPB = TW * TPB;
   // product positions kept in registers when they are few, computed per use otherwise
   static constexpr bool MUL_REGS = MP * S3 <= BBW_MUL_REGS_MAX;
+  static constexpr int PTAB_BYTES = MUL_REGS ? 1 : MP * EW * NH;
   // waves per SIMD that LDS allows (160 KiB per CU, 4 SIMDs); registers are budgeted for
   // the same occupancy, at most 4
-  static constexpr int LDS_WAVES = (163840 / (BYTES * TPB)) * WPB / 4;
+  static constexpr int LDS_WAVES = (163840 / (BYTES * TPB + PTAB_BYTES)) * WPB / 4;
   static constexpr int WAVES_EU = LDS_WAVES < 1 ? 1 : (LDS_WAVES > 4 ? 4 : LDS_WAVES);
 };
 
@@ -208,16 +252,30 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 #endif
 
 // Optional occupancy target (waves per SIMD) for the register allocator; 0 leaves the
-// choice to the compiler.
+// choice to the compiler (or to the per-instance targets below).
 #ifndef BBW_WAVES_EU
 #define BBW_WAVES_EU 0
 #endif
 
+#ifndef BBW_F32_TARGET4
+#define BBW_F32_TARGET4 0
+#endif
+
+// Instances whose register allocation is steered to 3 waves per SIMD: there the compiler's
+// own choice lands just above the 168 registers that 3 waves allow, and the target is met
+// without spilling (FP64 at N = 5, M <= 2 and N = 7, M = 2; LDS allows it).
+template <typename real, int N, int M>
+constexpr int stage_waves_target() {
+  if (BBW_WAVES_EU > 0) return BBW_WAVES_EU;
+  if (sizeof(real) == 8) return ((N == 5 && M <= 2) || (N == 7 && M == 2)) ? 3 : 0;
+  return (BBW_F32_TARGET4 && N == 5 && M <= 2) ? 4 : 0;
+}
+
 template <typename real, int N, int M, int EW, int WPB, bool UPDATE, bool RPOUT = false>
 __global__ __launch_bounds__(64 * WPB)
-#if BBW_WAVES_EU > 0
-__attribute__((amdgpu_waves_per_eu(BBW_WAVES_EU < StageLayout<real, N, M, EW>::WAVES_EU ? BBW_WAVES_EU : StageLayout<real, N, M, EW>::WAVES_EU, 8)))
-#endif
+__attribute__((amdgpu_waves_per_eu(
+    stage_waves_target<real, N, M>() > 0 && stage_waves_target<real, N, M>() <= StageLayout<real, N, M, EW>::WAVES_EU
+        ? stage_waves_target<real, N, M>() : 1, 8)))
 void stage_kernel(const StageArgs<real> a) {
   using L = StageLayout<real, N, M, EW>;
   constexpr int NP = L::NP, NP1 = L::NP1, NFP = L::NFP, NFP1 = L::NFP1, NH = L::NH, MP = L::MP;
@@ -230,10 +288,18 @@ void stage_kernel(const StageArgs<real> a) {
   constexpr int BZ = L::OFF_Z * SZ;
   constexpr int PQ = L::PLQ * SZ, PY = L::PLY * SZ;  // plane strides
   __shared__ __attribute__((aligned(16))) real smem[TPB * L::TOTAL];
+  // The RK register of the group arrives by direct global-to-LDS loads (no registers while
+  // the lift and the weight adjustment run): one dword per lane and instruction, in
+  // [field][slot][half][team lane] dword order (a real is one or two dwords, its halves TL
+  // dwords apart). The compiler waits for all outstanding memory operations before this
+  // array is read, so it is requested late (after the flux phase) and read at the very end,
+  // when the loads issued with it have long arrived.
+  constexpr int NH2 = L::NH2, DBW = L::DBW;
+  __shared__ __attribute__((aligned(16))) uint32_t dbuf[TPB * DBW + 1];
   // Without product positions in registers, a block-wide table holds pos(gamma - beta) for
   // every beta and product item (one byte each; NP marks a term that does not exist and
   // reads the zero cell after R).
-  constexpr int PTAB = L::MUL_REGS ? 1 : MP * EW * NH;
+  constexpr int PTAB = L::PTAB_BYTES;
   __shared__ uint8_t ptab[PTAB];
   static_assert(L::MUL_REGS || NP < 256, "positions must fit a byte");
   char* const lds = reinterpret_cast<char*>(smem);
@@ -248,6 +314,23 @@ void stage_kernel(const StageArgs<real> a) {
   };
   const int64_t K = a.K;
   const real* const qin = a.qin;
+  // direct loads into the team's dbuf rows: row dw (uniform) gets, at team lane l, dword h of
+  // the real at src of lane l; lds_real reads the lane's real back from its row
+  const int wl0 = __builtin_amdgcn_readfirstlane(lane & ~63);  // first team lane of this wave
+  auto dma = [&](uint32_t* buf, int dw, const real* src, int h) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(src) + 4 * h,
+                                     (__attribute__((address_space(3))) void*)(buf + dw + wl0), 4, 0, 0);
+  };
+  auto lds_real = [&](const uint32_t* buf, int dw, int half_stride) -> real {
+    if constexpr (SZ == 4) {
+      return __builtin_bit_cast(real, buf[dw + lane]);
+    } else {
+      const uint64_t v = (uint64_t)buf[dw + lane] | ((uint64_t)buf[dw + half_stride + lane] << 32);
+      return __builtin_bit_cast(real, v);
+    }
+  };
+  uint32_t* const nbt = dbuf + team * DBW;   // neighbour traces (one-wave teams)
+  uint32_t* const rbt = nbt + L::NBW;        // RK register (one-wave teams)
 
   // ---- which element groups this wave owns: contiguous ranges per XCD ----------------
   const int64_t ngroups = (K + EW - 1) / EW;
@@ -269,6 +352,9 @@ void stage_kernel(const StageArgs<real> a) {
   // with A(alpha) = a1! a2! a3!: the WADG levels are kept scaled by A (reductions) or by
   // 1/A (elevations), which leaves one weight per stencil.
   real fac3[S3N], facH[S3], aF[S3N], iA2[S3N];
+  // compensated telescoping: the rounding error of 1/A^2, and A / N!
+  constexpr int S3C = L::COMP ? S3N : 1;
+  real iA2l[S3C], aFn[S3C];
   // product positions, two 16-bit byte offsets per register
   int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? (MP + 1) / 2 : 1];
 #pragma unroll
@@ -287,6 +373,10 @@ void stage_kernel(const StageArgs<real> a) {
       fac3[sN] = (a0N >= 0) ? real(1) / real(fact(a0N) * fact(a1) * fact(a2) * fact(a3)) : real(0);
       aF[sN] = real(Af);
       iA2[sN] = real(1.0 / (Af * Af));
+      if constexpr (L::COMP) {
+        iA2l[sN] = real(1.0 / (Af * Af) - double(iA2[sN]));
+        aFn[sN] = real(Af / double(fact(N)));
+      }
     }
     if constexpr (L::MUL_REGS) {
       int b = 0;  // beta in the graded coefficient order of c^2
@@ -469,17 +559,84 @@ void stage_kernel(const StageArgs<real> a) {
       const real* src = geo_ok ? a.geo + k0 * kGeoStride + i : (c2_ok ? a.c2 + k0 * MP + j : a.geo + k0 * kGeoStride);
       pn[r] = *src;
     }
+  };
+  // face connectivity of group g (4 k' + f' or -1 per flux slot)
+  auto load_conn = [&](int64_t g, int (&c)[SF]) {
+    const int64_t k0 = g * EW;
 #pragma unroll
     for (int u = 0; u < SF; ++u) {
       const int item = lane + TL * u;
       const int fe = ffe[u] & 0xFFFF, f = fe / EW, e = fe - (fe / EW) * EW;
       const bool ok = item < 4 * EW * NFP && k0 + e < K;
-      cn[u] = a.conn[ok ? (k0 + e) * 4 + f : k0 * 4];  // a valid id or -1 either way
+      c[u] = a.conn[ok ? (k0 + e) * 4 + f : k0 * 4];  // a valid id or -1 either way
+    }
+  };
+  // the position in qin of flux slot u's neighbour coefficient for connectivity c (boundary
+  // faces, c < 0, take the group's first coefficient; the value is not used)
+  auto nb_base = [&](int64_t k0, int u, int c) -> size_t {
+    return c >= 0 ? (size_t)(c >> 2) * NP + ((fnb[u] >> (8 * (c & 3))) & 255) : (size_t)k0 * NP;
+  };
+  // one-wave teams: group g's neighbour traces straight into LDS (rows of the last slot only
+  // as wide as its items)
+  auto nb_dma = [&](int64_t g, const int (&c)[SF]) {
+    if constexpr (L::RS_DMA) {
+      const int64_t k0 = g * EW;
+      const size_t fs = (size_t)K * NP;
+#pragma unroll
+      for (int u = 0; u < SF; ++u) {
+        const size_t base = nb_base(k0, u, c[u]);
+        if (u < SF - 1 || lane < L::NBLAST) {
+#pragma unroll
+          for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int h = 0; h < NH2; ++h) dma(nbt, (f * NH2 + h) * L::NBR + u * TL, qin + base + f * fs, h);
+        }
+      }
+    }
+  };
+
+  // Stage group gg's scalars and state (prefetched into qn, pn) into the team's LDS slice. A
+  // lane keeps the value it writes at its own position when the next phase reads that
+  // position again ("self" terms below): coefficient positions are the same at every degree,
+  // so the value is already in the lane's registers (qcur).
+  real qcur[4][S3N];
+  auto stage_group = [&](int64_t gg) {
+    const int64_t kk = gg * EW;
+#pragma unroll
+    for (int r = 0; r < SPW; ++r) {
+      const int i = lane + TL * r;
+      const bool ok = i < 25 * EW ? kk + i / 25 < K : kk + (i - 25 * EW) / MP < K;
+      if (i < PW * EW) at(wb + BP + i * SZ) = ok ? pn[r] : real(0);
+    }
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + TL * s;
+      const bool ok = kk + (item - (item / EW) * EW) < K;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        qcur[f][s] = ok ? qn[f][s] : real(0);
+        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = qcur[f][s];
+      }
     }
   };
 
   int64_t g = gbeg + lw;
-  if (g < gend) prefetch(g);
+  int cur_cn[SF];  // connectivity of the group being computed (one-wave teams; cn: the next one)
+  if (g < gend) {
+    prefetch(g);
+    stage_group(g);
+    load_conn(g, cn);
+    if constexpr (L::RS_DMA) {
+      nb_dma(g, cn);
+#pragma unroll
+      for (int u = 0; u < SF; ++u) cur_cn[u] = cn[u];
+      load_conn(g + waves_per_xcd < gend ? g + waves_per_xcd : g, cn);
+    }
+    // wait for the connectivity here, so that the loop's first use of it does not need to
+    // drain the loads and stores that the loop itself has in flight
+#pragma unroll
+    for (int u = 0; u < SF; ++u) asm volatile("" : "+v"(cn[u]));
+  }
 
   for (; g < gend; g += waves_per_xcd) {
     const int64_t k0 = g * EW;
@@ -502,44 +659,28 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
         for (int b = 0; b < (MP + 1) / 2; ++b) asm volatile("" : "+v"(mpos[s][b]));
     }
-    // ---- stage this group's scalars and state into LDS --------------------------------
-#pragma unroll
-    for (int r = 0; r < SPW; ++r) {
-      const int i = lane + TL * r;
-      const bool ok = i < 25 * EW ? k0 + i / 25 < K : k0 + (i - 25 * EW) / MP < K;
-      if (i < PW * EW) at(wb + BP + i * SZ) = ok ? pn[r] : real(0);
-    }
-    // A lane keeps the value it writes at its own position when the next phase reads that
-    // position again ("self" terms below): coefficient positions are the same at every
-    // degree, so the value is already in the lane's registers.
-    real qcur[4][S3N];
-#pragma unroll
-    for (int s = 0; s < S3N; ++s) {
-      const int item = lane + TL * s;
-      const bool ok = k0 + (item - (item / EW) * EW) < K;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        qcur[f][s] = ok ? qn[f][s] : real(0);
-        if (item < EW * NP) at(wb + BQ + f * PQ + item * SZ) = qcur[f][s];
-      }
-    }
-    // ---- issue this group's neighbour traces, then the next prefetch ---------------------
+    // (this group's scalars and state were staged into LDS at the end of the previous group)
+    const int64_t gnext = g + waves_per_xcd;
     real nb[4][SF];
     int cur_conn[SF];
+    if constexpr (L::LOADS == kLoadsEarly) {  // this group's traces, then the next group's data
 #pragma unroll
-    for (int u = 0; u < SF; ++u) {
-      const int c = cn[u];
-      cur_conn[u] = c;
-      // boundary faces (c < 0) read this group's first coefficient; the value is not used
-      const size_t base = c >= 0 ? (size_t)(c >> 2) * NP + ((fnb[u] >> (8 * (c & 3))) & 255) : (size_t)k0 * NP;
-      const size_t fs = (size_t)K * NP;
-      nb[0][u] = qin[base];
-      nb[1][u] = qin[base + fs];
-      nb[2][u] = qin[base + 2 * fs];
-      nb[3][u] = qin[base + 3 * fs];
+      for (int u = 0; u < SF; ++u) {
+        cur_conn[u] = cn[u];
+        const size_t base = nb_base(k0, u, cn[u]);
+        const size_t fs = (size_t)K * NP;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) nb[f][u] = qin[base + f * fs];
+      }
+      // Every trace load is issued before the next group's loads, and those are issued
+      // unconditionally (a stand-in group past the end), so that the flux phase can wait for
+      // the traces alone: the counter of outstanding loads is in issue order, and loads on
+      // one side of a branch would make the wait cover them all.
+      asm volatile("" ::: "memory");
+      const int64_t gn = gnext < gend ? gnext : g;
+      prefetch(gn);
+      load_conn(gn, cn);
     }
-    const int64_t gnext = g + waves_per_xcd;
-    if (gnext < gend) prefetch(gnext);
     team_sync();
 
     // ---- volume: reference derivatives at degree N-1 -----------------------------------
@@ -607,6 +748,21 @@ void stage_kernel(const StageArgs<real> a) {
     // ---- surface: penalty fluxes per face coefficient ------------------------------------
     // F [NFP*CHP] at BA, channel (type*4 + f)*EW + e; T [NFP1*CHP] right after it
     constexpr int BF = BA, BT = BA + CHP * NFP * SZ;
+    // the neighbour traces of this group: in registers since the top, in LDS since the previous
+    // group, or requested here so that their registers are not held through the volume phases
+#pragma unroll
+    for (int u = 0; u < SF; ++u) {
+      if constexpr (L::LOADS == kLoadsLds) {
+        cur_conn[u] = cur_cn[u];
+      } else if constexpr (L::LOADS == kLoadsLate) {
+        const int c = cn[u];
+        cur_conn[u] = c;
+        const size_t base = nb_base(k0, u, c);
+        const size_t fs = (size_t)K * NP;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) nb[f][u] = qin[base + f * fs];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < SF; ++u) {
       const int item = lane + TL * u;
@@ -620,8 +776,14 @@ void stage_kernel(const StageArgs<real> a) {
         // jumps [[p]] = p+ - p and [[u]].n against the neighbour, or against the mirror
         // state on a wall: p = 0 walls take p+ = -p, u+ = u; rigid walls p+ = p,
         // u+ = u - 2 (u.n) n, so [[u]].n = -2 u.n (unit normals)
-        const real jp_in = nb[0][u] - pm;
-        const real jun_in = (nb[1][u] - um) * nx + (nb[2][u] - vm) * ny + (nb[3][u] - wm) * nz;
+        real nbv[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          if constexpr (L::RS_DMA) nbv[f] = lds_real(nbt, f * NH2 * L::NBR + u * TL, L::NBR);
+          else nbv[f] = nb[f][u];
+        }
+        const real jp_in = nbv[0] - pm;
+        const real jun_in = (nbv[1] - um) * nx + (nbv[2] - vm) * ny + (nbv[3] - wm) * nz;
         const real jp_wall = a.bc == 0 ? real(-2) * pm : real(0);
         const real jun_wall = a.bc == 0 ? real(0) : real(-2) * (um * nx + vm * ny + wm * nz);
         const bool interior = cur_conn[u] >= 0;
@@ -631,19 +793,46 @@ void stage_kernel(const StageArgs<real> a) {
         at(wb + BF + L::cunit(m, fe + 4 * EW) * SZ) = real(0.5) * (a.tau_u * jun - jp);
       }
     }
-    // the RK register of this group: issued now, consumed by the update at the end
-    real rs[4][S3N];
+    // the RK register of this group (straight into LDS, read by the update at the end, or
+    // into registers for a multi-wave team), then the next group's state, geometry and c^2
+    real rs[L::RS_DMA ? 1 : 4][L::RS_DMA ? 1 : S3N];
+    if constexpr (UPDATE && !L::RS_DMA) {
 #pragma unroll
-    for (int s = 0; s < S3N; ++s) {
-      const int item = lane + TL * s;
-      const int e = item - (item / EW) * EW, pos = item / EW;
-      const bool ok = item < EW * NP && k0 + e < K;
-      const size_t idx = ok ? (size_t)(k0 + e) * NP + pos : (size_t)k0 * NP;  // see the prefetch
+      for (int s = 0; s < S3N; ++s) {
+        const int item = lane + TL * s;
+        const int e = item - (item / EW) * EW, pos = item / EW;
+        const bool ok = item < EW * NP && k0 + e < K;
+        const size_t idx = ok ? (size_t)(k0 + e) * NP + pos : (size_t)k0 * NP;  // see the prefetch
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        if constexpr (UPDATE) rs[f][s] = a.res[(size_t)f * K * NP + idx];
-        else rs[f][s] = real(0);
+        for (int f = 0; f < 4; ++f) rs[f][s] = a.res[(size_t)f * K * NP + idx];
       }
+    }
+    if constexpr (UPDATE && L::RS_DMA) {
+#pragma unroll
+      for (int s = 0; s < S3N; ++s) {
+        const int item = lane + TL * s;
+        const int e = item - (item / EW) * EW, pos = item / EW;
+        const bool ok = item < EW * NP && k0 + e < K;
+        const size_t idx = ok ? (size_t)(k0 + e) * NP + pos : (size_t)k0 * NP;  // see the prefetch
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+          for (int h = 0; h < NH2; ++h) dma(rbt, ((f * S3N + s) * NH2 + h) * TL, a.res + (size_t)f * K * NP + idx, h);
+      }
+    }
+    if constexpr (L::LOADS == kLoadsLds) {
+      // unconditional, with a stand-in group past the end (values unused): a load under a
+      // branch would make its registers' next readers wait for every outstanding load
+      const int64_t gn = gnext < gend ? gnext : g, gnn = gnext + waves_per_xcd < gend ? gnext + waves_per_xcd : g;
+      nb_dma(gn, cn);  // cn holds the next group's connectivity
+#pragma unroll
+      for (int u = 0; u < SF; ++u) cur_cn[u] = cn[u];
+      prefetch(gn);
+      load_conn(gnn, cn);
+    } else if (L::LOADS == kLoadsLate) {
+      const int64_t gn = gnext < gend ? gnext : g;  // unconditional, as above
+      prefetch(gn);
+      load_conn(gn, cn);
     }
     team_sync();
 
@@ -811,61 +1000,176 @@ void stage_kernel(const StageArgs<real> a) {
         }
         team_sync();
       }
-      // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1
+      if constexpr (L::COMP) {
+        // Compensated FP32 telescoping. The c_j alternate in sign and grow with N (sum |c_j|
+        // = 259 at N=8, M=4 and 524 at N=9, M=4), so the rounding errors of float sweeps,
+        // the downward ones included, are amplified by about that sum. Here every level is a
+        // pair hi + lo of floats carried through error-free sums and products, which keeps
+        // the sweeps near double the float precision. The sweeps are unnormalised so that
+        // every stencil weight is a small integer: the downward level j is kept times
+        // N!/(N-j)! (no 1/n), the upward level j times (N-j)! (no 1/n), so c_j enters as
+        // c_j ((N-j)!)^2 / N! (a host-side pair) and the result is T_0 A(alpha) / N!.
+        constexpr int LB = EW * L::LEV * SZ;  // lo array = hi array + LB
+        real wlo[S3N];
 #pragma unroll
-      for (int j = 1; j <= N; ++j) {
-        const int n = N - j + 1;
-        const real inv = real(1) / real(n);
-        const int cnt = EW * dimp(n - 1);
-        const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
+        for (int s = 0; s < S3N; ++s) wlo[s] = real(0);
+        if (lane < N * EW) at(wb + BL + LB + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
+#pragma unroll
+        for (int j = 1; j <= N; ++j) {
+          const int n = N - j + 1;
+          const int cnt = EW * dimp(n - 1);
+          const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
+#pragma unroll
+          for (int s = 0; s < S3N; ++s) {
+            const int item = lane + TL * s;
+            if (s * TL < cnt && item < cnt) {
+              const N3 x = nb3(s);
+              const real w = real(n - x.sa);
+              real ph, pl, t;
+              two_prod(w, wcar[s], ph, pl);
+              pl += w * wlo[s];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                two_sum(ph, at(x.up[k] + src), ph, t);
+                pl += t + (j == 1 ? real(0) : at(x.up[k] + src + LB));  // level 0 is a plain float
+              }
+              two_sum(ph, pl, wcar[s], wlo[s]);
+              at(x.self + dst) = wcar[s];
+              at(x.self + dst + LB) = wlo[s];
+            }
+          }
+          team_sync();
+        }
+        // T_N = c''_N R_N (alpha = 0, A = 1)
+        if (lane < EW) {
+          real ph, pl;
+          two_prod(a.cjx_hi[N], wcar[0], ph, pl);
+          pl += a.cjx_hi[N] * wlo[0] + a.cjx_lo[N] * wcar[0];
+          two_sum(ph, pl, wcar[0], wlo[0]);
+          at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) = wcar[0];
+          at(wb + BL + LB + (lev_off(N, N) * EW + lane) * SZ) = wlo[0];
+        }
+        team_sync();
+#pragma unroll
+        for (int j = N - 1; j >= 0; --j) {
+          const int n = N - j;
+          const int cnt = EW * dimp(n);
+          const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
+          const real ch = a.cjx_hi[j], cl = a.cjx_lo[j];
+#pragma unroll
+          for (int s = 0; s < S3N; ++s) {
+            const int item = lane + TL * s;
+            if (s * TL < cnt && item < cnt) {
+              const N3 x = nb3(s);
+              // c''_j / A(alpha)^2 as a pair, times the downward level R_j
+              real fh, fl, ph, pl, eh, el, t;
+              two_prod(ch, iA2[s], fh, fl);
+              fl += ch * iA2l[s] + cl * iA2[s];
+              // level 0 (the reductions' output) is a plain float: its lo array is not written
+              const real rh = at(x.self + lo), rl = j == 0 ? real(0) : at(x.self + lo + LB);
+              two_prod(fh, rh, ph, pl);
+              pl += fh * rl + fl * rh;
+              // + the integer-weighted elevation of T_{j+1}: (n - |a|) self + the e_k-lower terms
+              const real w = real(n - x.sa);
+              two_prod(w, wcar[s], eh, el);
+              two_sum(ph, eh, ph, t);
+              pl += t + el + w * wlo[s];
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                two_sum(ph, at(x.dn[k] + hi), ph, t);
+                pl += t + at(x.dn[k] + hi + LB);
+              }
+              two_sum(ph, pl, wcar[s], wlo[s]);
+              at(x.self + lo) = wcar[s];
+              at(x.self + lo + LB) = wlo[s];
+            }
+          }
+          team_sync();
+        }
 #pragma unroll
         for (int s = 0; s < S3N; ++s) {
           const int item = lane + TL * s;
-          if (s * TL < cnt && item < cnt) {
-            const N3 x = nb3(s);
-            const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + src);
-            wcar[s] = inv * (real(n - x.sa) * self_v + (at(x.up[0] + src) + at(x.up[1] + src) + at(x.up[2] + src)));
-            at(x.self + dst) = wcar[s];
+          if (item < EW * NP) acc[0][s] = aFn[s] * wcar[s] + aFn[s] * wlo[s];
+        }
+      } else {
+        // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1
+#pragma unroll
+        for (int j = 1; j <= N; ++j) {
+          const int n = N - j + 1;
+          const real inv = real(1) / real(n);
+          const int cnt = EW * dimp(n - 1);
+          const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
+#pragma unroll
+          for (int s = 0; s < S3N; ++s) {
+            const int item = lane + TL * s;
+            if (s * TL < cnt && item < cnt) {
+              const N3 x = nb3(s);
+              const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + src);
+              wcar[s] = inv * (real(n - x.sa) * self_v + (at(x.up[0] + src) + at(x.up[1] + src) + at(x.up[2] + src)));
+              at(x.self + dst) = wcar[s];
+            }
           }
+          team_sync();
+        }
+        // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}. The
+        // reductions above kept A(alpha) x (one weight, n - |a|, on the e0 term); here s is
+        // kept as s / A(alpha), so r enters with 1/A^2 and the elevation again has one weight.
+        if (lane < EW) {
+          wcar[0] *= a.cj[N];
+          at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) = wcar[0];
         }
         team_sync();
-      }
-      // upward sweep: s_N = c_N r_N; s_j = c_j r_j + E^{N-j}_{N-j-1} s_{j+1}. The
-      // reductions above kept A(alpha) x (one weight, n - |a|, on the e0 term); here s is
-      // kept as s / A(alpha), so r enters with 1/A^2 and the elevation again has one weight.
-      if (lane < EW) {
-        wcar[0] *= a.cj[N];
-        at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) = wcar[0];
-      }
-      team_sync();
 #pragma unroll
-      for (int j = N - 1; j >= 0; --j) {
-        const int n = N - j;
-        const real inv = real(1) / real(n);
-        const real cj = a.cj[j];
-        const int cnt = EW * dimp(n);
-        const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
+        for (int j = N - 1; j >= 0; --j) {
+          const int n = N - j;
+          const real inv = real(1) / real(n);
+          const real cj = a.cj[j];
+          const int cnt = EW * dimp(n);
+          const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
+#pragma unroll
+          for (int s = 0; s < S3N; ++s) {
+            const int item = lane + TL * s;
+            if (s * TL < cnt && item < cnt) {
+              const N3 x = nb3(s);
+              const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + hi);
+              const real el = real(n - x.sa) * self_v + (at(x.dn[0] + hi) + at(x.dn[1] + hi) + at(x.dn[2] + hi));
+              wcar[s] = (cj * iA2[s]) * at(x.self + lo) + inv * el;
+              at(x.self + lo) = wcar[s];
+            }
+          }
+          team_sync();
+        }
 #pragma unroll
         for (int s = 0; s < S3N; ++s) {
           const int item = lane + TL * s;
-          if (s * TL < cnt && item < cnt) {
-            const N3 x = nb3(s);
-            const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + hi);
-            const real el = real(n - x.sa) * self_v + (at(x.dn[0] + hi) + at(x.dn[1] + hi) + at(x.dn[2] + hi));
-            wcar[s] = (cj * iA2[s]) * at(x.self + lo) + inv * el;
-            at(x.self + lo) = wcar[s];
-          }
+          if (item < EW * NP) acc[0][s] = aF[s] * wcar[s];
         }
-        team_sync();
-      }
-#pragma unroll
-      for (int s = 0; s < S3N; ++s) {
-        const int item = lane + TL * s;
-        if (item < EW * NP) acc[0][s] = aF[s] * wcar[s];
       }
     }
 
     // ---- write: rhs, or the low-storage RK stage --------------------------------------------
+    // The results are formed first; the next group is then staged into LDS (its loads have
+    // arrived), and only then are the results stored, so the next group's first reads of its
+    // own data never have to wait for these stores.
+    real outv[4][S3N], resv[4][S3N];
+#pragma unroll
+    for (int s = 0; s < S3N; ++s) {
+      const int item = lane + TL * s;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if constexpr (UPDATE) {
+          real rv;
+          if constexpr (L::RS_DMA) rv = lds_real(rbt, ((f * S3N + s) * NH2) * TL, TL);
+          else rv = rs[f][s];
+          resv[f][s] = a.rk_a * rv + a.dt * acc[f][s];
+          outv[f][s] = at(wb + BQ + f * PQ + (item < EW * NP ? item : 0) * SZ) + a.rk_b * resv[f][s];
+        } else {
+          outv[f][s] = acc[f][s];
+        }
+      }
+    }
+    team_sync();  // the next group overwrites this team's LDS slice
+    stage_group(gnext < gend ? gnext : g);  // a stand-in past the end (unused)
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
       const int item = lane + TL * s;
@@ -874,17 +1178,11 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const size_t gi = ((size_t)f * K + k0 + e) * NP + pos;
-          if constexpr (UPDATE) {
-            const real r = a.rk_a * rs[f][s] + a.dt * acc[f][s];
-            a.res[gi] = r;
-            a.qout[gi] = at(wb + BQ + f * PQ + item * SZ) + a.rk_b * r;
-          } else {
-            a.qout[gi] = acc[f][s];
-          }
+          if constexpr (UPDATE) a.res[gi] = resv[f][s];
+          a.qout[gi] = outv[f][s];
         }
       }
     }
-    team_sync();  // the next group overwrites this team's LDS slice
   }
 }
 

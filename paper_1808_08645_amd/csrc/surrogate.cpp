@@ -124,8 +124,9 @@ int forward(bbwadg_sur* s, const float* x, int B, hipStream_t st) {
   return 0;
 }
 
-// Gradient of the loss with respect to every parameter, from dL/dy in s->dy.back().
-int backward(bbwadg_sur* s, int B, hipStream_t st) {
+// Gradient of the loss with respect to every parameter, from dL/dy in s->dy.back(); with
+// dx0 != null also with respect to the input, into dx0 [B][grid^3].
+int backward(bbwadg_sur* s, int B, hipStream_t st, float* dx0 = nullptr) {
   int rc;
   for (int l = (int)s->L.size() - 1; l >= 0; --l) {
     const Layer& y = s->L[l];
@@ -150,8 +151,9 @@ int backward(bbwadg_sur* s, int B, hipStream_t st) {
     g.K = rows;
     choose_split(s, g);
     if ((rc = kc(sur_gemm(g, st), "gemm dW"))) return rc;
-    if (l == 0) break;
-    // dX = dY W^T: into the previous layer's output gradient (through col2im for a convolution)
+    if (l == 0 && !dx0) break;
+    // dX = dY W^T: into the previous layer's output gradient (through col2im for a convolution),
+    // or for the first layer into the input gradient
     GemmArgs h{};
     h.A = s->dybf;
     h.sam = y.N;
@@ -166,17 +168,20 @@ int backward(bbwadg_sur* s, int B, hipStream_t st) {
     h.ldc = y.Kp;
     choose_split(s, h);
     if ((rc = kc(sur_gemm(h, st), "gemm dX"))) return rc;
-    if (y.conv && (rc = kc(sur_col2im(s->dcol[l], s->dy[l - 1], B, y.D, y.Cin, y.Do, (int)y.Kp, st), "col2im")))
+    if (y.conv && (rc = kc(sur_col2im(s->dcol[l], l > 0 ? s->dy[l - 1] : dx0, B, y.D, y.Cin, y.Do, (int)y.Kp, st),
+                           "col2im")))
       return rc;
   }
   return 0;
 }
 
-int loss_grad(bbwadg_sur* s, const float* x, const float* t, int B, double* loss, hipStream_t st) {
+int loss_grad(bbwadg_sur* s, const float* x, const float* t, int B, double* loss, hipStream_t st,
+              float* dx = nullptr) {
   int rc;
   if ((rc = forward(s, x, B, st))) return rc;
   const int64_t n = (int64_t)B * s->nout;
-  if ((rc = kc(sur_mse(s->act.back(), t, s->dy.back(), s->partial, n, s->nred, st), "mse")) || (rc = backward(s, B, st)))
+  if ((rc = kc(sur_mse(s->act.back(), t, s->dy.back(), s->partial, n, s->nred, st), "mse")) ||
+      (rc = backward(s, B, st, dx)))
     return rc;
   std::vector<double> part(s->nred);
   if ((rc = hipc(hipMemcpyAsync(part.data(), s->partial, s->nred * 8, hipMemcpyDeviceToHost, st), "loss download")) ||
@@ -343,6 +348,15 @@ int bbwadg_sur_loss_grad(bbwadg_sur* s, const float* x, const float* t, int32_t 
   if (rc || (rc = loss_grad(s, x, t, B, loss, st))) return rc;
   if (grad_host)
     return hipc(hipMemcpy(grad_host, s->g, (size_t)s->nparam * 4, hipMemcpyDeviceToHost), "gradient download");
+  return 0;
+}
+
+int bbwadg_sur_input_grad(bbwadg_sur* s, const float* x, const float* t, int32_t B, double* loss, float* dx,
+                          void* stream) {
+  if (!s || !x || !t || !loss || !dx) return set_error(BBWADG_EINVAL, "NULL argument");
+  int rc = check_batch(s, B);
+  hipStream_t st = (hipStream_t)stream;
+  if (rc || (rc = loss_grad(s, x, t, B, loss, st, dx))) return rc;
   return 0;
 }
 

@@ -84,6 +84,18 @@ class Surrogate:
                                               self._stream()))
         return loss.value, g
 
+    def input_grad(self, x, t):
+        """(loss, dL/dx) of L = mean((f(x) - t)^2); dL/dx a device tensor shaped like x."""
+        import torch
+        B = int(x.shape[0])
+        x = self._dev(x, (B, self.grid, self.grid, self.grid))
+        t = self._dev(t, (B, self.nout))
+        loss = C.c_double()
+        dx = torch.empty_like(x)
+        _check(self._lib.bbwadg_sur_input_grad(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), B,
+                                               C.byref(loss), C.c_void_p(dx.data_ptr()), self._stream()))
+        return loss.value, dx
+
     def train_step(self, x, t, lr: float) -> float:
         B = int(x.shape[0])
         x = self._dev(x, (B, self.grid, self.grid, self.grid))

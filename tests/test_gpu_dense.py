@@ -4,8 +4,8 @@
   projection is exact for that rule: paper Theorem 5.3 against eq. pwadg).
 * With the true c^2 at the points it must equal the oracle's plain WADG mode (c^2 point
   values at the same collapsed rule, dense quadrature matrices in an orthonormal basis).
-Tolerance 1e-11 relative L2 per field (FP64); sizes span several 16-element tiles and a
-ragged tail.
+Tolerance 1e-11 relative L2 per field in FP64, 1e-5 in FP32 (FP32 matrix cores with FP32
+accumulation); sizes span several 16-element tiles and a ragged tail.
 """
 import numpy as np
 import pytest
@@ -16,6 +16,7 @@ from workloads import c2_gaussian_bumps, c2_sinusoid, kuhn_cube_mesh, random_c2_
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
+TOL32 = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -33,11 +34,12 @@ def _compare(o, q_gpu, Q_oracle):
     return o.rel_l2(a, b)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("N,M", [(1, 1), (2, 1), (3, 1), (4, 2), (5, 2), (6, 3), (7, 3), (8, 4), (9, 4)])
-def test_dense_with_c2M_equals_bernstein_rhs(bb, N, M):
-    print(f"[dense = bbwadg] N={N} M={M}", flush=True)
+def test_dense_with_c2M_equals_bernstein_rhs(bb, N, M, dtype):
+    print(f"[dense = bbwadg] N={N} M={M} {dtype}", flush=True)
     xyz, etov = kuhn_cube_mesh(2)
-    s = bb.Solver(xyz, etov, N, M)
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
     s.set_c2(random_c2_coefficients(61, s.K, s.Mp))
     q = s.to_device(random_state(62, s.K, s.Np))
     s.dense_set_c2(None)
@@ -45,35 +47,45 @@ def test_dense_with_c2M_equals_bernstein_rhs(bb, N, M):
     b = s.rhs_dense(q)
     o = Oracle(xyz, etov, N, M)
     o.set_c2_bernstein(s.get_c2())
-    ref = o.rhs(o.from_bernstein(q.cpu().numpy()))
-    assert np.all(_compare(o, a, ref) < TOL)
-    assert np.all(_compare(o, b, ref) < TOL), _compare(o, b, ref)
+    ref = o.rhs(o.from_bernstein(q.double().cpu().numpy()))
+    # The FP32 dense update sums its Nq-point products against the entries of P_q, whose size
+    # grows with N (the Bernstein mass matrix's inverse): measured 1.6e-5 (N=8) and 3.1e-5
+    # (N=9) on the pressure, so those degrees are held to 5e-5.
+    tol = TOL if dtype == "f64" else (TOL32 if N <= 7 else 5e-5)
+    assert np.all(_compare(o, a, ref) < tol)
+    assert np.all(_compare(o, b, ref) < tol), _compare(o, b, ref)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("K_sel", [1, 7, 17, 48])
-@pytest.mark.parametrize("N,M", [(3, 1), (5, 2)])
-def test_dense_true_c2_matches_oracle_wadg(bb, K_sel, N, M):
+@pytest.mark.parametrize("N,M", [(3, 1), (5, 2), (8, 2)])
+def test_dense_true_c2_matches_oracle_wadg(bb, K_sel, N, M, dtype):
     """Quadrature WADG of the true c^2 (the paper's comparison method)."""
-    print(f"[dense true c2] K={K_sel} N={N} M={M}", flush=True)
+    print(f"[dense true c2] K={K_sel} N={N} M={M} {dtype}", flush=True)
     xyz, etov = kuhn_cube_mesh(2)
     etov = etov[:K_sel]
-    s = bb.Solver(xyz, etov, N, M)
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
     s.dense_set_c2(c2_gaussian_bumps(3))
     q = s.to_device(random_state(63, s.K, s.Np))
     out = s.rhs_dense(q)
     o = Oracle(xyz, etov, N, M)
     o.set_c2_function(c2_gaussian_bumps(3), project=False)
-    err = _compare(o, out, o.rhs(o.from_bernstein(q.cpu().numpy())))
-    assert np.all(err < TOL), err
+    err = _compare(o, out, o.rhs(o.from_bernstein(q.double().cpu().numpy())))
+    print(f"  rel L2 per field {err}", flush=True)
+    # In FP32 the dense products round against the entries of P_q = M^-1 V_q^T W, whose size
+    # grows with N (the Bernstein mass matrix's inverse), so N = 8 is held to 1e-4.
+    tol = TOL if dtype == "f64" else (TOL32 if N <= 5 else 1e-4)
+    assert np.all(err < tol), err
 
 
-def test_dense_update_in_place_and_full_size_sample(bb):
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dense_update_in_place_and_full_size_sample(bb, dtype):
     """196,608 tets, N=5, M=2: the update alone, in place and out of place, against the
-    fast projection on a sample of elements (c^2_M at the points)."""
+    fast projection (c^2_M at the points)."""
     import torch
-    print("[dense full size]", flush=True)
+    print(f"[dense full size] {dtype}", flush=True)
     xyz, etov = kuhn_cube_mesh(32)
-    s = bb.Solver(xyz, etov, 5, 2)
+    s = bb.Solver(xyz, etov, 5, 2, dtype=dtype)
     s.project_c2(c2_sinusoid)
     s.dense_set_c2(None)
     q = s.to_device(random_state(64, s.K, s.Np))
@@ -85,11 +97,12 @@ def test_dense_update_in_place_and_full_size_sample(bb):
     # the fast path computes the same projection: compare through the full right-hand sides
     a = s.rhs(q)
     b = s.rhs_dense(q)
-    rel = torch.linalg.norm(a - b) / torch.linalg.norm(a)
-    assert float(rel) < 1e-12, float(rel)
+    rel = torch.linalg.norm((a - b).double()) / torch.linalg.norm(a.double())
+    assert float(rel) < (1e-12 if dtype == "f64" else 1e-5), float(rel)
 
 
 def test_dense_error_paths(bb):
+    import torch
     print("[dense errors]", flush=True)
     xyz, etov = kuhn_cube_mesh(1)
     s = bb.Solver(xyz, etov, 3, 1)
@@ -103,8 +116,5 @@ def test_dense_error_paths(bb):
     with pytest.raises(bb.BBWADGError) as ei:
         s.dense_set_c2(lambda x, y, z: 1.0 - 2.0 * x)  # not positive everywhere
     assert ei.value.code == -3
-    s32 = bb.Solver(xyz, etov, 3, 1, dtype="f32")
-    s32.set_c2(np.ones((s32.K, s32.Mp)))
-    with pytest.raises(bb.BBWADGError) as ei:
-        s32.dense_set_c2(None)
-    assert ei.value.code == -1
+    with pytest.raises(ValueError):  # an update input of the other precision
+        s.dense_update(torch.zeros((s.K, s.Np), dtype=torch.float32, device="cuda"))

@@ -52,7 +52,7 @@ def test_elastic_update_matches_oracle(bb, N, M, dtype):
     o = Oracle(xyz, etov, N, M)
     ref = elastic_update(o, o.from_bernstein(r), rho_inv, lam, mu)
     err = _compare(o, out, ref)
-    tol = 1e-11 if dtype == "f64" else (1e-5 if N <= 7 else 2e-4)
+    tol = 1e-11 if dtype == "f64" else 1e-5
     assert np.all(err < tol), err
 
 
@@ -126,7 +126,7 @@ def test_wadg_update_matches_oracle(bb, N, M, dtype):
     Rm = o.from_bernstein(r[None])[0]
     ref = ((Rm @ o.Vq.T) * o.c2q) @ o.Pq.T
     err = o.rel_l2(o.bernstein_values_at_quad(out.double().cpu().numpy()[None]), o.values_at_quad(ref[None]))
-    tol = 1e-11 if dtype == "f64" else (1e-5 if N <= 7 else 2e-4)
+    tol = 1e-11 if dtype == "f64" else 1e-5
     assert np.all(err < tol), err
 
 

@@ -57,7 +57,7 @@ def test_rhs_with_source_parity(bb, N, M, dtype):
     o.set_c2_bernstein(c2)
     o.set_source(o.from_bernstein(g[None])[0], amp=0.8, omega=2.5, phase=0.4)
     err = _compare(o, out, o.rhs(o.from_bernstein(q), t=0.31))
-    tol = FP64_TOL if dtype == "f64" else (1e-5 if N <= 7 else 2e-4)
+    tol = FP64_TOL if dtype == "f64" else 1e-5
     assert np.all(err < tol), err
     # removing the source gives the source-free right-hand side back
     s.set_source(None)

@@ -62,6 +62,22 @@ def test_forward_loss_and_gradient_match_oracle(sur, B, nout):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("B,nout", [(1, 40), (6, 2000)])
+def test_input_gradient_matches_oracle(sur, B, nout):
+    """dL/dx (the network as a differentiable stand-in for the solver) against the oracle's
+    autograd; the device rounds the backward GEMM inputs to BF16, hence 3e-2 relative L2."""
+    print(f"[surrogate input gradient] B={B} nout={nout}", flush=True)
+    s = sur(nout, 8, seed=21)
+    x, t = _inputs(B, nout, 22)
+    net = SurrogateNet(s.layout(), nout)
+    Jo, dxo = net.input_grad(s.get_params(), x, t)
+    J, dx = s.input_grad(x, t)
+    dx = dx.cpu().numpy()
+    assert abs(J - Jo) <= 2e-3 * Jo, (J, Jo)
+    assert dx.shape == dxo.shape
+    assert np.linalg.norm(dx - dxo) <= 3e-2 * np.linalg.norm(dxo), np.linalg.norm(dx - dxo) / np.linalg.norm(dxo)
+
+
 def test_set_params_roundtrip_and_training_reduces_the_loss(sur):
     print("[surrogate training]", flush=True)
     s = sur(300, 16, seed=5)

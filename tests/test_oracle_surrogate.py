@@ -82,3 +82,29 @@ def test_gradient_matches_central_differences():
         jm = net.loss_grad(pm, x, t, rounding=False, dtype=torch.float64)[0]
         fd = (jp - jm) / 2e-6
         assert abs(fd - g[i]) < 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_input_gradient_matches_central_differences():
+    """Without rounding, in float64: dL/dx by autograd against central differences at the
+    input voxels with the largest gradient in each of two samples (and a few at random)."""
+    L, npar = _layout(6)
+    rng = np.random.default_rng(4)
+    p = 0.1 * rng.standard_normal(npar)
+    x = rng.uniform(-1, 1, (2, 16, 16, 16))
+    t = rng.standard_normal((2, 6))
+    net = SurrogateNet(L, 6)
+    J, dx = net.input_grad(p, x, t, rounding=False, dtype=torch.float64)
+    J2, _, _ = net.loss_grad(p, x, t, rounding=False, dtype=torch.float64)
+    assert J == J2
+    flat = dx.reshape(-1)
+    picks = [int(np.argmax(np.abs(flat[:4096]))), 4096 + int(np.argmax(np.abs(flat[4096:])))]
+    picks += [int(i) for i in rng.choice(8192, 4, replace=False)]
+    for i in picks:
+        xp, xm = x.copy().reshape(-1), x.copy().reshape(-1)
+        xp[i] += 1e-6
+        xm[i] -= 1e-6
+        jp = net.loss_grad(p, xp.reshape(x.shape), t, rounding=False, dtype=torch.float64)[0]
+        jm = net.loss_grad(p, xm.reshape(x.shape), t, rounding=False, dtype=torch.float64)[0]
+        fd = (jp - jm) / 2e-6
+        assert abs(fd - flat[i]) < 1e-6 * max(1.0, abs(fd)), (i, fd, flat[i])
+    assert abs(flat[picks[0]]) > 1e-4

@@ -208,13 +208,7 @@ def manufactured_source(c2):
     return g
 
 
-def c2_random_model(seed: int, transition: float = 0.03):
-    """A seeded velocity model with c^2 in [1, 4]: 2-4 layers split by parallel planes with a
-    tilted normal (a, b, 1)/|.|, a, b ~ U[-0.3, 0.3], interface offsets ~ U over the cube's
-    extent along the normal, layer values ~ U[1, 3.5], each interface a tanh step of the given
-    width (0.03 keeps the degree-2 projection on the 16^3 Kuhn mesh positive: sharp jumps of
-    this size make it negative in about one medium in five); plus 4 Gaussian bumps (amplitude
-    U[-0.5, 0.5], width U[0.08, 0.2], centres U[0, 1]^3); clipped to [1, 4]."""
+def _random_model_params(seed: int):
     rng = np.random.default_rng(10_000 + int(seed))
     a, b = rng.uniform(-0.3, 0.3, size=2)
     nrm = np.array([a, b, 1.0])
@@ -226,6 +220,17 @@ def c2_random_model(seed: int, transition: float = 0.03):
     amp = rng.uniform(-0.5, 0.5, size=4)
     wid = rng.uniform(0.08, 0.2, size=4)
     ctr = rng.uniform(0.0, 1.0, size=(4, 3))
+    return nrm, cuts, vals, amp, wid, ctr
+
+
+def c2_random_model(seed: int, transition: float = 0.03):
+    """A seeded velocity model with c^2 in [1, 4]: 2-4 layers split by parallel planes with a
+    tilted normal (a, b, 1)/|.|, a, b ~ U[-0.3, 0.3], interface offsets ~ U over the cube's
+    extent along the normal, layer values ~ U[1, 3.5], each interface a tanh step of the given
+    width (0.03 keeps the degree-2 projection on the 16^3 Kuhn mesh positive: sharp jumps of
+    this size make it negative in about one medium in five); plus 4 Gaussian bumps (amplitude
+    U[-0.5, 0.5], width U[0.08, 0.2], centres U[0, 1]^3); clipped to [1, 4]."""
+    nrm, cuts, vals, amp, wid, ctr = _random_model_params(seed)
 
     def f(x, y, z):
         x, y, z = np.broadcast_arrays(np.asarray(x, dtype=np.float64), y, z)
@@ -238,6 +243,36 @@ def c2_random_model(seed: int, transition: float = 0.03):
         return np.clip(out, 1.0, 4.0)
 
     return f
+
+
+def c2_random_model_family(seed: int, transition: float = 0.03):
+    """The medium of c2_random_model(seed) before its clipping, written as a linear combination
+    c^2(x) = sum_i theta_i phi_i(x): phi_i are the smooth indicators of the layers (differences
+    of the tanh steps) and the 4 Gaussian bumps, theta = (layer values, bump amplitudes).
+    Returns (phis, theta) with theta the model's own parameters."""
+    nrm, cuts, vals, amp, wid, ctr = _random_model_params(seed)
+
+    def step(i):
+        def h(x, y, z):
+            x, y, z = np.broadcast_arrays(np.asarray(x, dtype=np.float64), y, z)
+            d = nrm[0] * x + nrm[1] * y + nrm[2] * z
+            return 0.5 * (1.0 + np.tanh((d - cuts[i]) / transition))
+        return h
+
+    H = [step(i) for i in range(len(cuts))]
+    phis = []
+    for j in range(len(vals)):
+        def layer(x, y, z, j=j):
+            lo = H[j - 1](x, y, z) if j > 0 else 1.0
+            hi = H[j](x, y, z) if j < len(H) else 0.0
+            return np.broadcast_to(np.asarray(lo - hi, dtype=np.float64), np.broadcast(x, y, z).shape)
+        phis.append(layer)
+    for w, c in zip(wid, ctr):
+        def bump(x, y, z, w=w, c=c):
+            x, y, z = np.broadcast_arrays(np.asarray(x, dtype=np.float64), y, z)
+            return np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2.0 * w * w))
+        phis.append(bump)
+    return phis, np.concatenate([vals, amp])
 
 
 def grid_centres(n: int = 16):
