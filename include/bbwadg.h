@@ -204,6 +204,18 @@ int bbwadg_suggest_dt(const bbwadg_ctx* ctx, double cfl, double* dt);
  * out: host double[4]. Synchronises `stream`. */
 int bbwadg_l2norm2(bbwadg_ctx* ctx, const void* q, double out[4], void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): bbwadg_l2norm2 with no allocation and no
+ * synchronisation. The per-block partial sums go to a fixed device array of the library
+ * (1,024 blocks x 4 doubles = 32 KiB on each GPU the library runs on, held until the
+ * process ends) and a second kernel adds them in block order into out, so the result equals
+ * bbwadg_l2norm2's bit for bit. q: device [4][K][Np] of the context dtype; out: device
+ * double[4], written asynchronously on `stream`. Every call on one GPU shares that array
+ * (each call writes all of the partial sums it reads), so calls that overlap on one GPU,
+ * e.g. on two streams, race. EINVAL for NULL arguments or when the current device is not
+ * the context's; EHIP for a launch error. */
+int bbwadg_l2norm2_noalloc(bbwadg_ctx* ctx, const void* q, double* out, void* stream);
+
 /* ---- FP64 quadrature reductions (L^2 errors as in the convergence study of paper
  * Section 6.1; the acoustic energy of eq. (awave), in which WADG is stable, Section 3) ----
  * Both evaluate the device state q [4][K][Np] at the points of the degree-N projection rule

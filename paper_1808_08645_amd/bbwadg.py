@@ -27,7 +27,7 @@ EXPORTS = (
     "bbwadg_element_vertices", "bbwadg_geometry", "bbwadg_projection_npoints",
     "bbwadg_projection_points", "bbwadg_project_samples", "bbwadg_project_c2",
     "bbwadg_set_c2", "bbwadg_get_c2", "bbwadg_rhs", "bbwadg_step", "bbwadg_suggest_dt",
-    "bbwadg_l2norm2", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
+    "bbwadg_l2norm2", "bbwadg_l2norm2_noalloc", "bbwadg_l2error2", "bbwadg_energy", "bbwadg_project_fn", "bbwadg_coef_index",
     "bbwadg_dense_npoints", "bbwadg_dense_points", "bbwadg_dense_set_c2", "bbwadg_dense_update",
     "bbwadg_rhs_dense", "bbwadg_set_source", "bbwadg_set_receivers", "bbwadg_receiver_elements",
     "bbwadg_misfit_gradient", "bbwadg_adjoint_apply", "bbwadg_elastic_set_media", "bbwadg_elastic_update",
@@ -94,6 +94,7 @@ def load_library(path: str = LIB_PATH):
         "bbwadg_step": (C.c_int, [vp, vp, vp, dbl, dbl, i32, vp]),
         "bbwadg_suggest_dt": (C.c_int, [vp, dbl, pd]),
         "bbwadg_l2norm2": (C.c_int, [vp, vp, pd, vp]),
+        "bbwadg_l2norm2_noalloc": (C.c_int, [vp, vp, vp, vp]),
         "bbwadg_l2error2": (C.c_int, [vp, vp, i64, i64, vp, pd, vp]),
         "bbwadg_energy": (C.c_int, [vp, vp, i64, i64, pd, vp]),
         "bbwadg_project_fn": (C.c_int, [vp, C2_CALLBACK, vp, i32, vp, vp]),
@@ -505,6 +506,19 @@ class Solver:
         self._check_state(q, "q")
         out = np.zeros(4)
         _check(self._lib.bbwadg_l2norm2(self._ctx, C.c_void_p(q.data_ptr()), _dptr(out), self._stream()))
+        return out
+
+    def l2norm2_noalloc(self, q, out=None):
+        """bbwadg_l2norm2_noalloc: the squared norms into a device double[4] tensor, with no
+        allocation and no synchronisation in the library (out is allocated here if None)."""
+        import torch
+        self._check_state(q, "q")
+        if out is None:
+            out = torch.empty(4, dtype=torch.float64, device=q.device)
+        if out.dtype != torch.float64 or out.numel() < 4 or not out.is_contiguous() or out.device != q.device:
+            raise ValueError("out must be a contiguous float64 device tensor of 4 values")
+        _check(self._lib.bbwadg_l2norm2_noalloc(self._ctx, C.c_void_p(q.data_ptr()), C.c_void_p(out.data_ptr()),
+                                                self._stream()))
         return out
 
     def l2error2(self, q, fns, k0: int = 0, k1: int | None = None, chunk: int = 16384) -> np.ndarray:

@@ -70,6 +70,15 @@ int launch_stage_f32(int N, int M, bool update, const StageArgs<float>& a, void*
 int launch_l2norm(int N, int dtype, const void* q, int64_t K, const double* J, const double* mass,
                   double* partial, int nblocks, void* stream);
 
+// The norm reduction without allocation (noalloc.hip): partial sums in a fixed device array
+// of kScratchBlocks x 4 doubles, added on the device into out (device double[4]).
+// scratch_init() resolves the array's address on the current device (once per device);
+// both return a hipError_t value cast to int.
+constexpr int kScratchBlocks = 1024;
+int scratch_init();
+int l2norm2_noalloc(int N, int dtype, const void* q, int64_t K, const double* J, const double* mass, int nblocks,
+                    double* out, void* stream);
+
 // Quadrature reductions over elements [k0, k1): mode 0 = squared L^2 error against
 // `exact`, mode 1 = the two halves of the acoustic energy (p^2/c^2 and |u_i|^2 terms).
 struct QuadReduceArgs {

@@ -888,6 +888,12 @@ int bbwadg_create(const bbwadg_mesh* mesh, const bbwadg_opts* opts, bbwadg_ctx**
     delete c;
     return rc;
   }
+  // the fixed scratch array of the allocation-free entry points, resolved on this device
+  if (int se = scratch_init()) {
+    free_device(c);
+    delete c;
+    return fail(BBWADG_EHIP, "scratch address: %s", hipGetErrorString((hipError_t)se));
+  }
   std::vector<ld> mass = bernstein_mass(N);
   std::vector<double> massd(mass.begin(), mass.end());
   if (rs == 8) {
@@ -1141,6 +1147,21 @@ int bbwadg_l2norm2(bbwadg_ctx* c, const void* q, double out[4], void* stream) {
     for (int b = 0; b < c->nred_blocks; ++b) acc += part[(size_t)b * 4 + f];
     out[f] = acc;
   }
+  return 0;
+}
+
+int bbwadg_l2norm2_noalloc(bbwadg_ctx* c, const void* q, double* out, void* stream) {
+  int rc = require_device(c);
+  if (rc) return rc;
+  if (!q || !out) return fail(BBWADG_EINVAL, "NULL argument");
+  if (c->nred_blocks > kScratchBlocks)
+    return fail(BBWADG_EINVAL, "%d reduction blocks exceed the fixed scratch of %d", c->nred_blocks, kScratchBlocks);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return fail(BBWADG_EINVAL, "the current device is not the context's device %d", c->device);
+  const int e = l2norm2_noalloc(c->N, c->dtype, q, c->K, (const double*)c->d_J, (const double*)c->d_mass,
+                                c->nred_blocks, out, stream);
+  if (e) return fail(BBWADG_EHIP, "l2norm (no allocation) launch: %s", hipGetErrorString((hipError_t)e));
   return 0;
 }
 
