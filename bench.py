@@ -240,7 +240,7 @@ def cpu_baseline(dt, steps):
             "sample": f"cube 16^3x6 = {K} tets, N={N}, M={M}, same medium and pulse, {steps} LSRK4 steps, FP64"}
 
 
-def c3_sweep(steps, warmup):
+def c3_sweep(steps, warmup, n_list=range(4, 10)):
     """The 196,608-tet mesh at N = 4..9, M = N/2, three-layer medium (c^2 in {1, 2, 4}, seed 1)
     projected to P^M, Gaussian pulse: FP64 and FP32 throughput and per-field FP32-vs-FP64
     relative L2 after warmup + steps LSRK4 steps (both legs share the c^2_M data).
@@ -256,7 +256,7 @@ def c3_sweep(steps, warmup):
     from workloads import c2_three_layer, ic_gaussian_pulse, kuhn_cube_mesh
     xyz, etov = kuhn_cube_mesh(CELLS)
     out = []
-    for n in range(4, 10):
+    for n in n_list:
         m = n // 2
         s64 = bb.Solver(xyz, etov, n, m, dtype="f64")
         s64.set_c2_policy(True)
@@ -308,10 +308,11 @@ def c3_sweep(steps, warmup):
     return out
 
 
-def wadg_compare(n_list, m_list, reps, cells=None):
-    """Dense quadrature WADG (matrix cores) against the Bernstein update on the 196,608-tet mesh:
-    times of the fused Bernstein right-hand side, the plain DG right-hand side (c^2 = 1, no
-    weight adjustment), and the dense update alone, with c^2_M of the bump medium at the points."""
+def wadg_compare(n_list, m_list, reps, cells=None, dtypes=("f64", "f32")):
+    """Dense quadrature WADG (matrix cores) against the Bernstein update on the 196,608-tet mesh,
+    in each precision: times of the fused Bernstein right-hand side, the plain DG right-hand
+    side (c^2 = 1, no weight adjustment), and the dense update alone, with c^2_M of the bump
+    medium at the points."""
     import torch
 
     import paper_1808_08645_amd as bb
@@ -330,39 +331,43 @@ def wadg_compare(n_list, m_list, reps, cells=None):
         return e0.elapsed_time(e1) / reps
 
     out = []
-    for n in n_list:
-        # the plain DG right-hand side: the fused kernel with M = 0 and c^2 = 1
-        s0 = bb.Solver(xyz, etov, n, 0, dtype="f64")
-        s0.set_c2(np.ones((s0.K, 1)))
-        q0 = s0.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s0.K, s0.Np)))
-        r0 = torch.empty_like(q0)
-        t_dg = timed(lambda: s0.rhs(q0, r0))
-        del s0, q0, r0
-        for m in m_list:
-            if m > n:
-                continue
-            s = bb.Solver(xyz, etov, n, m, dtype="f64")
-            s.project_c2(c2_bumps_medium())
-            s.dense_set_c2(None)
-            q = s.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s.K, s.Np)))
-            r = torch.empty_like(q)
-            t_bb = timed(lambda: s.rhs(q, r))
-            t_dense_rhs = timed(lambda: s.rhs_dense(q, r))
-            p0 = q[0].contiguous()
-            p1 = torch.empty_like(p0)
-            t_dense = timed(lambda: s.dense_update(p0, p1))
-            t_bupd = timed(lambda: s.wadg_update(p0, p1))
-            e = {"N": n, "M": m, "Np": s.Np, "nq_dense": s.dense_npoints(), "rhs_bernstein_ms": t_bb,
-                 "rhs_dense_ms": t_dense_rhs, "dense_update_ms": t_dense, "plain_dg_rhs_ms": t_dg,
-                 "bernstein_update_ms": t_bupd, "fused_minus_plain_ms": t_bb - t_dg,
-                 "elements": s.K, "bernstein_update_us_per_element": t_bupd * 1e3 / s.K,
-                 "dense_update_us_per_element": t_dense * 1e3 / s.K,
-                 "bernstein_update_gb_s": (2 * s.Np + s.Mp) * 8 * s.K / (t_bupd * 1e-3) / 1e9,
-                 "dense_update_tflops": 4.0 * s.dense_npoints() * s.Np * s.K / (t_dense * 1e-3) / 1e12}
-            out.append(e)
-            print(json.dumps({"wadg_compare_progress": e}), file=sys.stderr, flush=True)
-            del s, q, r, p0, p1
-            torch.cuda.empty_cache()
+    for dtype in dtypes:
+        word = 8 if dtype == "f64" else 4
+        for n in n_list:
+            # the plain DG right-hand side: the fused kernel with M = 0 and c^2 = 1
+            s0 = bb.Solver(xyz, etov, n, 0, dtype=dtype)
+            s0.set_c2(np.ones((s0.K, 1)))
+            q0 = s0.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s0.K, s0.Np)))
+            r0 = torch.empty_like(q0)
+            t_dg = timed(lambda: s0.rhs(q0, r0))
+            del s0, q0, r0
+            for m in m_list:
+                if m > n:
+                    continue
+                s = bb.Solver(xyz, etov, n, m, dtype=dtype)
+                s.project_c2(c2_bumps_medium())
+                s.dense_set_c2(None)
+                q = s.to_device(np.random.default_rng(5).uniform(-1, 1, (4, s.K, s.Np)))
+                r = torch.empty_like(q)
+                t_bb = timed(lambda: s.rhs(q, r))
+                t_dense_rhs = timed(lambda: s.rhs_dense(q, r))
+                p0 = q[0].contiguous()
+                p1 = torch.empty_like(p0)
+                t_dense = timed(lambda: s.dense_update(p0, p1))
+                t_bupd = timed(lambda: s.wadg_update(p0, p1))
+                e = {"dtype": dtype, "N": n, "M": m, "Np": s.Np, "nq_dense": s.dense_npoints(),
+                     "rhs_bernstein_ms": t_bb, "rhs_dense_ms": t_dense_rhs, "dense_update_ms": t_dense,
+                     "plain_dg_rhs_ms": t_dg, "bernstein_update_ms": t_bupd, "fused_minus_plain_ms": t_bb - t_dg,
+                     "elements": s.K, "bernstein_update_us_per_element": t_bupd * 1e3 / s.K,
+                     "dense_update_us_per_element": t_dense * 1e3 / s.K,
+                     "bernstein_update_gb_s": (2 * s.Np + s.Mp) * word * s.K / (t_bupd * 1e-3) / 1e9,
+                     "dense_update_tflops": 4.0 * s.dense_npoints() * s.Np * s.K / (t_dense * 1e-3) / 1e12,
+                     "dense_update_frac_of_mfma_peak": 4.0 * s.dense_npoints() * s.Np * s.K / (t_dense * 1e-3) / 1e12
+                     / (78.6 if dtype == "f64" else 157.3)}
+                out.append(e)
+                print(json.dumps({"wadg_compare_progress": e}), file=sys.stderr, flush=True)
+                del s, q, r, p0, p1
+                torch.cuda.empty_cache()
     return out
 
 
@@ -645,6 +650,8 @@ def main():
                     help="instead of the default workload: dense quadrature WADG vs the Bernstein update, N = 2..9")
     ap.add_argument("--c3", action="store_true",
                     help="instead of the default workload: N = 4..9, M = N/2 on the three-layer medium, FP64 and FP32")
+    ap.add_argument("--c3-n", type=str, default="4,5,6,7,8,9", help="degrees of the --c3 sweep (profiling)")
+    ap.add_argument("--wadg-compare-dtypes", type=str, default="f64,f32")
     ap.add_argument("--rates", action="store_true",
                     help="instead of the default workload: manufactured-solution errors and rates, N = 1..6, M = 0..3")
     ap.add_argument("--adjoint", action="store_true",
@@ -670,7 +677,8 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     if args.wadg_compare:
-        res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps), args.wadg_compare_cells)
+        res = wadg_compare(range(2, 10), (1, 2), max(1, args.steps), args.wadg_compare_cells,
+                           tuple(args.wadg_compare_dtypes.split(",")))
         k = 6 * args.wadg_compare_cells ** 3
         print(json.dumps({"workload": f"cube {args.wadg_compare_cells}^3x6 = {k} tets, bump medium, c^2_M at the dense points",
                           "unit": "ms per evaluation",
@@ -699,7 +707,7 @@ def main():
                           "dtype": "f64", "rates": res}), flush=True)
         return
     if args.c3:
-        res = c3_sweep(args.steps, args.warmup)
+        res = c3_sweep(args.steps, args.warmup, [int(v) for v in args.c3_n.split(",")])
         print(json.dumps({"metric": "GDOF-updates/s per RK step (FP32 vs FP64) + % HBM peak, at stated L2 error",
                           "unit": "GDOF-updates/s", "workload": "cube196k_N4-9_three_layer", "steps": args.steps,
                           "warmup": args.warmup, "data": "synthetic", "c3": res}), flush=True)

@@ -15,25 +15,9 @@ constexpr int kMaxDeg = kMaxN + kMaxM;
 __host__ __device__ constexpr int dimp(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) * (n + 3) / 6; }
 __host__ __device__ constexpr int dim2(int n) { return n < 0 ? 0 : (n + 1) * (n + 2) / 2; }
 
-// Error-free transformations of float arithmetic (Knuth's two-sum; the FMA product
-// error): s + e == a + b and p + e == a b exactly. Contraction is switched off so that the
-// sums are the rounded sums the formulas assume.
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-#pragma clang fp contract(off)
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
-#pragma clang fp contract(off)
-  p = a * b;
-  e = __builtin_fmaf(a, b, -p);
-}
-
-
-// Smallest degree whose FP32 kernels run the telescoped projection in float pairs.
-#ifndef BBW_COMP_MIN_N
-#define BBW_COMP_MIN_N 8
+// Smallest degree whose FP32 kernels run the telescoped projection in FP64.
+#ifndef BBW_TELE64_MIN_N
+#define BBW_TELE64_MIN_N 8
 #endif
 
 // Per-element geometry record: G[9] (G[3i+j] = d r_j / d x_i), then for each face f:
@@ -56,8 +40,7 @@ struct StageArgs {
   real src_amp;           // s(t) of the source f = s(t) g(x) at this stage's time
   real* rp_out;           // [K][Np] r_p before the weight adjustment (source included), or null (step mode)
   real cj[kMaxN + 1];     // telescoped projection coefficients c_j
-  // c_j ((N-j)!)^2 / N! as a pair hi + lo of reals (the compensated FP32 telescoping)
-  real cjx_hi[kMaxN + 1], cjx_lo[kMaxN + 1];
+  double cjd[kMaxN + 1];  // the c_j in FP64 (FP32 kernels that run the telescoping in FP64)
 };
 
 // Launch one fused stage (UPDATE) or one right-hand-side evaluation on `stream`.
@@ -125,7 +108,7 @@ struct ElasticArgs {
   const real* mu;
   int64_t K;
   real cj[kMaxN + 1];
-  real cjx_hi[kMaxN + 1], cjx_lo[kMaxN + 1];  // as in StageArgs
+  double cjd[kMaxN + 1];  // as in StageArgs
   // optional low-storage RK stage in place of out (res != nullptr): res = rk_a res + dt u,
   // q += rk_b res, u the update of r; res, q [9][K][Np]
   real* res;

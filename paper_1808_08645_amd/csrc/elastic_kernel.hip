@@ -13,6 +13,8 @@
 // Coefficients are in the graded order of the library, pos(a1, a2, a3) =
 // dimp(s-1) + a3 (2s + 3 - a3)/2 + a2 with s = a1 + a2 + a3, the same position at every
 // degree >= s, so a lane keeps one multi-index per slot across all levels.
+#include <type_traits>
+
 #include "bbwadg_internal.hpp"
 
 namespace bbw {
@@ -50,17 +52,17 @@ constexpr int elastic_tables() {  // product positions (bytes), stencil table (1
 }
 // NC = 9: the elastic update (9 inputs and the trace, 3 media); NC = 1: one field and one
 // weight (the acoustic update Pi_N(c^2_M r)).
-// FP32 projections of degree N >= BBW_COMP_MIN_N run the telescoping in float pairs (a
-// second, lo, array of levels): the alternating c_j amplify the rounding of float sweeps.
+// FP32 projections of degree N >= BBW_TELE64_MIN_N run the telescoping in FP64 (the levels
+// as doubles): the alternating c_j amplify the rounding of float sweeps.
 template <typename real, int N, int M>
-constexpr bool elastic_comp() {
-  return sizeof(real) == 4 && N >= BBW_COMP_MIN_N && M > 0;
+constexpr bool elastic_tele64() {
+  return sizeof(real) == 4 && N >= BBW_TELE64_MIN_N && M > 0;
 }
 template <typename real, int N, int M, int NC>
 constexpr int elastic_per_wave(int G) {
   constexpr int XF = NC == 9 ? 10 : 1, NW = NC == 9 ? 3 : 1;
-  constexpr int LV = (elastic_comp<real, N, M>() ? 2 : 1) * lev_base(N, N + 1);
-  return (XF * dimp(N) + NW * dimp(M) + G * (dimp(N + M) + dimp(N + M - 1) + LV)) * (int)sizeof(real);
+  constexpr int LV = (elastic_tele64<real, N, M>() ? 2 : 1) * lev_base(N, N + 1);
+  return (XF * dimp(N) + NW * dimp(M) + G * (dimp(N + M) + dimp(N + M - 1) + LV) + 2) * (int)sizeof(real);
 }
 
 // LDS bytes a wavefront's buffers may take when choosing the group size (occupancy against
@@ -91,9 +93,10 @@ struct ElasticLayout {
   static constexpr int LEV = lev_base(N, N + 1);  // levels r_0 .. r_N
   static constexpr int XF = NC == 9 ? 10 : 1, NW = NC == 9 ? 3 : 1;
   static constexpr int G = elastic_group<real, N, M, NC>(), WAVES = elastic_waves<real, N, M, NC>();
-  static constexpr bool COMP = elastic_comp<real, N, M>();
+  static constexpr bool TELE64 = elastic_tele64<real, N, M>();
+  // the levels start 8-byte aligned (doubles with TELE64), and so does every wave's slice
   static constexpr int OFF_X = 0, OFF_W = XF * NP, OFF_A = OFF_W + NW * MP, OFF_B = OFF_A + G * NH,
-                       OFF_L = OFF_B + G * NB, OFF_LL = OFF_L + G * LEV, TOTAL = OFF_LL + (COMP ? G * LEV : 0);
+                       OFF_L = (OFF_B + G * NB + 1) / 2 * 2, TOTAL = (OFF_L + (TELE64 ? 2 : 1) * G * LEV + 1) / 2 * 2;
 };
 
 template <typename real, int N, int M, int NC>
@@ -101,7 +104,7 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
   using L = ElasticLayout<real, N, M, NC>;
   constexpr int NP = L::NP, NH = L::NH, MP = L::MP, NB = L::NB, LEV = L::LEV, G = L::G, WPB = L::WAVES;
   static_assert(NP < 255, "product positions must fit a byte");
-  __shared__ real smem[WPB * L::TOTAL];
+  __shared__ __attribute__((aligned(16))) real smem[WPB * L::TOTAL];
   __shared__ uint8_t ptab[MP * NH];
   __shared__ uint4 itab[NH];
   __shared__ real facH[NH];
@@ -111,7 +114,7 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
   real* const A = smem + wave * L::TOTAL + L::OFF_A;
   real* const B = smem + wave * L::TOTAL + L::OFF_B;
   real* const LV = smem + wave * L::TOTAL + L::OFF_L;
-  real* const LVL = smem + wave * L::TOTAL + L::OFF_LL;  // lo parts of the levels (L::COMP)
+  double* const LVD = reinterpret_cast<double*>(smem + wave * L::TOTAL + L::OFF_L);  // the levels (L::TELE64)
 
   // ---- per-block tables -------------------------------------------------------------
   // itab[i] for the multi-index a at graded position i (s = |a|, D(s) = (s+1)(s+2)/2):
@@ -151,18 +154,19 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
   }
   __syncthreads();
 
-  // one reduction (E^n_{n-1})^T over G components: y_a = [(a0+1) x_a + sum_j (a_j+1) x_{a+e_j}] / n
-  auto reduce = [&](const real* src, int sst, real* dst, int dstr, int n) {
+  // one reduction (E^n_{n-1})^T over G components: y_a = [(a0+1) x_a + sum_j (a_j+1) x_{a+e_j}] / n,
+  // in the source's precision (stored in the destination's)
+  auto reduce = [&](const auto* src, int sst, auto* dst, int dstr, int n) {
+    using T = std::remove_cv_t<std::remove_pointer_t<decltype(src)>>;
     const int cnt = dimp(n - 1);
-    const real inv = real(1) / real(n);
+    const T inv = T(1) / T(n);
     for (int t = lane; t < G * cnt; t += 64) {
       const int cl = t / cnt, i = t - cl * cnt;
       const uint4 e = itab[i];
       const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - 1 - (int)(e.w >> 8);
-      const real* x = src + cl * sst;
+      const T* x = src + cl * sst;
       const int u1 = e.x & 0xFFFF, u3 = e.x >> 16;
-      dst[cl * dstr + i] =
-          inv * (real(a0 + 1) * x[i] + real(a1 + 1) * x[u1] + real(a2 + 1) * x[u1 + 1] + real(a3 + 1) * x[u3]);
+      dst[cl * dstr + i] = inv * (T(a0 + 1) * x[i] + T(a1 + 1) * x[u1] + T(a2 + 1) * x[u1 + 1] + T(a3 + 1) * x[u3]);
     }
     wsync();
   };
@@ -220,6 +224,10 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
 #pragma unroll
         for (int n = N + M; n > N; --n) {
           const bool last = n - 1 == N;
+          if (L::TELE64 && last) {
+            reduce(src, sst, LVD, LEV, n);  // level 0, widened
+            break;
+          }
           real* dst = last ? LV : (src == A ? B : A);
           const int dstr = last ? LEV : (src == A ? NB : NH);
           reduce(src, sst, dst, dstr, n);
@@ -227,83 +235,32 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
           sst = dstr;
         }
       }
-      if constexpr (L::COMP) {
-        // Compensated FP32 telescoping: each level is a pair hi + lo of floats carried through
-        // error-free sums and products. The sweeps are unnormalised so that every weight is a
-        // small integer: the downward level j is kept times N!/(N-j)! and the upward one times
-        // (N-j)!, so c_j enters as c_j ((N-j)!)^2 / N! (host-side pairs) and the result is
-        // (hi + lo) / N!.
+      if constexpr (L::TELE64) {
+        // FP64 telescoping (FP32 state): the sweeps below on doubles, the result rounded to
+        // float into A (free once the reductions are done), where the writes read it
 #pragma unroll
-        for (int j = 1; j <= N; ++j) {
-          const int n = N - j + 1, cnt = dimp(n - 1);
-          for (int t = lane; t < G * cnt; t += 64) {
-            const int cl = t / cnt, i = t - cl * cnt;
-            const uint4 e = itab[i];
-            const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - 1 - (int)(e.w >> 8);
-            const real* x = LV + cl * LEV + lev_base(N, j - 1);
-            const real* xl = LVL + cl * LEV + lev_base(N, j - 1);
-            const int u1 = e.x & 0xFFFF, u3 = e.x >> 16;
-            const int idx[4] = {i, u1, u1 + 1, u3};
-            const real w[4] = {real(a0 + 1), real(a1 + 1), real(a2 + 1), real(a3 + 1)};
-            real ph, pl, th, tl, t2;
-            two_prod(w[0], x[idx[0]], ph, pl);
-#pragma unroll
-            for (int k = 1; k < 4; ++k) {
-              two_prod(w[k], x[idx[k]], th, tl);
-              two_sum(ph, th, ph, t2);
-              pl += t2 + tl;
-            }
-            if (j > 1)  // level 0 is a plain float
-#pragma unroll
-              for (int k = 0; k < 4; ++k) pl += w[k] * xl[idx[k]];
-            two_sum(ph, pl, LV[cl * LEV + lev_base(N, j) + i], LVL[cl * LEV + lev_base(N, j) + i]);
-          }
-          wsync();
-        }
-        if (lane < G) {
-          real* h = LV + lane * LEV + lev_base(N, N);
-          real* l = LVL + lane * LEV + lev_base(N, N);
-          real ph, pl;
-          two_prod(a.cjx_hi[N], *h, ph, pl);
-          pl += a.cjx_hi[N] * *l + a.cjx_lo[N] * *h;
-          two_sum(ph, pl, *h, *l);
-        }
+        for (int j = 1; j <= N; ++j) reduce(LVD + lev_base(N, j - 1), LEV, LVD + lev_base(N, j), LEV, N - j + 1);
+        if (lane < G) LVD[lane * LEV + lev_base(N, N)] *= a.cjd[N];
         wsync();
 #pragma unroll
         for (int j = N - 1; j >= 0; --j) {
           const int n = N - j, cnt = dimp(n);
-          const real ch = a.cjx_hi[j], cl_ = a.cjx_lo[j];
+          const double cj = a.cjd[j], inv = 1.0 / double(n);
           for (int t = lane; t < G * cnt; t += 64) {
             const int cl = t / cnt, i = t - cl * cnt;
             const uint4 e = itab[i];
             const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - (int)(e.w >> 8);
-            real* lo = LV + cl * LEV + lev_base(N, j);
-            real* lol = LVL + cl * LEV + lev_base(N, j);
-            const real* hi = LV + cl * LEV + lev_base(N, j + 1);
-            const real* hil = LVL + cl * LEV + lev_base(N, j + 1);
-            real ph, pl, th, tl, t2;
-            two_prod(ch, lo[i], ph, pl);
-            pl += cl_ * lo[i];
-            if (j > 0) pl += ch * lol[i];  // level 0 is a plain float: its lo array is not written
-            // integer-weighted elevation of the level above (a zero weight skips a term)
-            const int idx[4] = {(int)(e.y & 0xFFFF), (int)(e.y >> 16), (int)(e.z & 0xFFFF), i};
-            const real w[4] = {real(a1), real(a2), real(a3), real(a0)};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              if (k == 3 && a0 <= 0) continue;  // position i of the level above exists for a0 > 0
-              two_prod(w[k], hi[idx[k]], th, tl);
-              two_sum(ph, th, ph, t2);
-              pl += t2 + tl + w[k] * hil[idx[k]];
-            }
-            two_sum(ph, pl, lo[i], lol[i]);  // only this item reads lo[i]
+            double* lo = LVD + cl * LEV + lev_base(N, j);
+            const double* hi = LVD + cl * LEV + lev_base(N, j + 1);
+            double el = double(a1) * hi[e.y & 0xFFFF] + double(a2) * hi[e.y >> 16] + double(a3) * hi[e.z & 0xFFFF];
+            if (a0 > 0) el += double(a0) * hi[i];
+            lo[i] = cj * lo[i] + inv * el;  // only this item reads lo[i]
           }
           wsync();
         }
-        // (hi + lo) / N! into the hi array, where the writes below read the result
-        constexpr real inv_nf = real(1.0 / factd(N));
         for (int t = lane; t < G * NP; t += 64) {
           const int cl = t / NP, i = t - cl * NP;
-          LV[cl * LEV + i] = LV[cl * LEV + i] * inv_nf + LVL[cl * LEV + i] * inv_nf;
+          A[cl * NP + i] = real(LVD[cl * LEV + i]);
         }
         wsync();
       } else {
@@ -330,6 +287,8 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
           wsync();
         }
       }
+      const real* RES = L::TELE64 ? A : LV;  // the projected group
+      constexpr int RST = L::TELE64 ? NP : LEV;
       if (a.res) {  // a low-storage RK stage (uniform branch); res and q never alias
         real* __restrict__ rs = a.res;
         real* __restrict__ qs = a.q;
@@ -337,14 +296,14 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
         for (int t = lane; t < G * NP; t += 64) {
           const int cl = t / NP, i = t - cl * NP;
           const size_t idx = ((size_t)(c0 + cl) * a.K + k) * NP + i;
-          const real r2 = a.rk_a * rs[idx] + a.dt * LV[cl * LEV + i];
+          const real r2 = a.rk_a * rs[idx] + a.dt * RES[cl * RST + i];
           rs[idx] = r2;
           qs[idx] += a.rk_b * r2;
         }
       } else {
         for (int t = lane; t < G * NP; t += 64) {
           const int cl = t / NP, i = t - cl * NP;
-          a.out[((size_t)(c0 + cl) * a.K + k) * NP + i] = LV[cl * LEV + i];
+          a.out[((size_t)(c0 + cl) * a.K + k) * NP + i] = RES[cl * RST + i];
         }
       }
       wsync();  // the buffers are reused by the next group and element

@@ -541,23 +541,14 @@ int sync_c2(bbwadg_ctx* ctx, hipStream_t s) {
   return 0;
 }
 
-// The c_j of the telescoped projection for a kernel's argument block, and the pairs
-// hi + lo = c_j ((N-j)!)^2 / N! of the compensated FP32 telescoping (unnormalised sweeps).
+// The c_j of the telescoped projection for a kernel's argument block, in the kernel's
+// precision and in FP64.
 template <typename Args>
 void set_cj(const bbwadg_ctx* c, Args& a) {
   using real = std::remove_reference_t<decltype(a.cj[0])>;
-  ld fn = 1;
-  for (int i = 2; i <= c->N; ++i) fn *= i;
   for (int j = 0; j <= kMaxN; ++j) {
     a.cj[j] = (real)c->tables.cj[j];
-    ld v = 0;
-    if (j <= c->N) {
-      ld f = 1;
-      for (int i = 2; i <= c->N - j; ++i) f *= i;
-      v = (ld)c->tables.cj[j] * f * f / fn;
-    }
-    a.cjx_hi[j] = (real)v;
-    a.cjx_lo[j] = (real)(v - (ld)a.cjx_hi[j]);
+    a.cjd[j] = (double)c->tables.cj[j];
   }
 }
 

@@ -170,10 +170,10 @@ struct StageLayout {
   static constexpr int NP = dimp(N), NP1 = dimp(N - 1), NFP = dim2(N), NFP1 = dim2(N - 1);
   static constexpr int NH = dimp(N + M), NH1 = dimp(N + M - 1), MP = dimp(M);
   static constexpr int LEV = lev_off(N, N + 1);
-  // FP32 telescoping in float pairs where the c_j amplify rounding most (N >= BBW_COMP_MIN_N);
-  // the levels then have a second (lo) array
-  static constexpr bool COMP = sizeof(real) == 4 && N >= BBW_COMP_MIN_N && M > 0;
-  static constexpr int LEVA = COMP ? 2 * LEV : LEV;
+  // FP32 state with the telescoping in FP64 where the c_j amplify rounding most
+  // (N >= BBW_TELE64_MIN_N); the levels are then doubles (+ 2 reals: 8-byte aligned start)
+  static constexpr bool TELE64 = sizeof(real) == 4 && N >= BBW_TELE64_MIN_N && M > 0;
+  static constexpr int LEVA = TELE64 ? 2 * LEV + 2 : LEV;
   static constexpr int PW = 25 + MP;                   // per-element scalars: geometry + c^2
   static constexpr int S3 = cdiv(EW * NH, TL);         // 3D slots (degree <= N+M)
   static constexpr int S3N = cdiv(EW * NP, TL);        // 3D slots covering degree N
@@ -352,9 +352,7 @@ void stage_kernel(const StageArgs<real> a) {
   // with A(alpha) = a1! a2! a3!: the WADG levels are kept scaled by A (reductions) or by
   // 1/A (elevations), which leaves one weight per stencil.
   real fac3[S3N], facH[S3], aF[S3N], iA2[S3N];
-  // compensated telescoping: the rounding error of 1/A^2, and A / N!
-  constexpr int S3C = L::COMP ? S3N : 1;
-  real iA2l[S3C], aFn[S3C];
+  double iA2d[L::TELE64 ? S3N : 1];  // 1/A^2 in FP64 (FP64 telescoping)
   // product positions, two 16-bit byte offsets per register
   int mpos[L::MUL_REGS ? S3 : 1][L::MUL_REGS ? (MP + 1) / 2 : 1];
 #pragma unroll
@@ -373,10 +371,7 @@ void stage_kernel(const StageArgs<real> a) {
       fac3[sN] = (a0N >= 0) ? real(1) / real(fact(a0N) * fact(a1) * fact(a2) * fact(a3)) : real(0);
       aF[sN] = real(Af);
       iA2[sN] = real(1.0 / (Af * Af));
-      if constexpr (L::COMP) {
-        iA2l[sN] = real(1.0 / (Af * Af) - double(iA2[sN]));
-        aFn[sN] = real(Af / double(fact(N)));
-      }
+      if constexpr (L::TELE64) iA2d[sN] = 1.0 / (Af * Af);
     }
     if constexpr (L::MUL_REGS) {
       int b = 0;  // beta in the graded coefficient order of c^2
@@ -928,11 +923,19 @@ void stage_kernel(const StageArgs<real> a) {
       team_sync();
       constexpr int NH1 = L::NH1;
       constexpr int BH = BB, BH1 = BB + EW * NH * SZ, BL = BH1 + EW * NH1 * SZ;
+      // FP64 levels: item u of a level at byte BLD + (level offset + u) * 8; a 3D offset
+      // o = wb + 4 u (float slots) maps to wb + 8 u by 2 o - wb
+      constexpr int BLD = (BL + 7) & ~7;
+      auto atd = [lds](int byteoff) -> double& { return *reinterpret_cast<double*>(lds + byteoff); };
+      auto dof = [wb](int off) { return 2 * off - wb; };
       real wcar[S3];  // the lane's own value of the previous WADG phase
 #pragma unroll
       for (int s = 0; s < S3; ++s) wcar[s] = real(0);
       // re-zero the guards in front of levels 1..N (the face chain shared this space)
-      if (lane < N * EW) at(wb + BL + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
+      if (lane < N * EW) {
+        if constexpr (L::TELE64) atd(wb + BLD + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * 8) = 0.0;
+        else at(wb + BL + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
+      }
       // h_gamma = sum_beta R_{gamma-beta} c2_beta/beta!
       real h[S3];
 #pragma unroll
@@ -995,93 +998,59 @@ void stage_kernel(const StageArgs<real> a) {
             const N3 x = nb3(s);
             const real self_v = (BBW_CARRY & 8) ? wcar[s] : at(x.self + src);
             wcar[s] = inv * (real(n - x.sa) * self_v + (at(x.up[0] + src) + at(x.up[1] + src) + at(x.up[2] + src)));
-            at(x.self + dst) = wcar[s];
+            if (L::TELE64 && n - 1 == N) atd(dof(x.self) + BLD) = double(wcar[s]);
+            else at(x.self + dst) = wcar[s];
           }
         }
         team_sync();
       }
-      if constexpr (L::COMP) {
-        // Compensated FP32 telescoping. The c_j alternate in sign and grow with N (sum |c_j|
-        // = 259 at N=8, M=4 and 524 at N=9, M=4), so the rounding errors of float sweeps,
-        // the downward ones included, are amplified by about that sum. Here every level is a
-        // pair hi + lo of floats carried through error-free sums and products, which keeps
-        // the sweeps near double the float precision. The sweeps are unnormalised so that
-        // every stencil weight is a small integer: the downward level j is kept times
-        // N!/(N-j)! (no 1/n), the upward level j times (N-j)! (no 1/n), so c_j enters as
-        // c_j ((N-j)!)^2 / N! (a host-side pair) and the result is T_0 A(alpha) / N!.
-        constexpr int LB = EW * L::LEV * SZ;  // lo array = hi array + LB
-        real wlo[S3N];
+      if constexpr (L::TELE64) {
+        // FP32 state, FP64 telescoping. The c_j alternate in sign and grow with N (sum |c_j|
+        // = 259 at N=8, M=4 and 524 at N=9, M=4), so float sweeps lose about that factor of
+        // their precision. Here the sweeps of the FP64 kernel run on doubles in LDS: level 0
+        // (the float reductions' output) is widened once and the result rounded to float.
+        double wd[S3N];
 #pragma unroll
-        for (int s = 0; s < S3N; ++s) wlo[s] = real(0);
-        if (lane < N * EW) at(wb + BL + LB + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
+        for (int s = 0; s < S3N; ++s) wd[s] = double(wcar[s]);
 #pragma unroll
         for (int j = 1; j <= N; ++j) {
           const int n = N - j + 1;
+          const double inv = 1.0 / double(n);
           const int cnt = EW * dimp(n - 1);
-          const int src = BL + lev_off(N, j - 1) * EW * SZ, dst = BL + lev_off(N, j) * EW * SZ;
+          const int src = BLD + lev_off(N, j - 1) * EW * 8, dst = BLD + lev_off(N, j) * EW * 8;
 #pragma unroll
           for (int s = 0; s < S3N; ++s) {
             const int item = lane + TL * s;
             if (s * TL < cnt && item < cnt) {
               const N3 x = nb3(s);
-              const real w = real(n - x.sa);
-              real ph, pl, t;
-              two_prod(w, wcar[s], ph, pl);
-              pl += w * wlo[s];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                two_sum(ph, at(x.up[k] + src), ph, t);
-                pl += t + (j == 1 ? real(0) : at(x.up[k] + src + LB));  // level 0 is a plain float
-              }
-              two_sum(ph, pl, wcar[s], wlo[s]);
-              at(x.self + dst) = wcar[s];
-              at(x.self + dst + LB) = wlo[s];
+              wd[s] = inv * (double(n - x.sa) * wd[s] +
+                             (atd(dof(x.up[0]) + src) + atd(dof(x.up[1]) + src) + atd(dof(x.up[2]) + src)));
+              atd(dof(x.self) + dst) = wd[s];
             }
           }
           team_sync();
         }
-        // T_N = c''_N R_N (alpha = 0, A = 1)
         if (lane < EW) {
-          real ph, pl;
-          two_prod(a.cjx_hi[N], wcar[0], ph, pl);
-          pl += a.cjx_hi[N] * wlo[0] + a.cjx_lo[N] * wcar[0];
-          two_sum(ph, pl, wcar[0], wlo[0]);
-          at(wb + BL + (lev_off(N, N) * EW + lane) * SZ) = wcar[0];
-          at(wb + BL + LB + (lev_off(N, N) * EW + lane) * SZ) = wlo[0];
+          wd[0] *= a.cjd[N];
+          atd(wb + BLD + (lev_off(N, N) * EW + lane) * 8) = wd[0];
         }
         team_sync();
 #pragma unroll
         for (int j = N - 1; j >= 0; --j) {
           const int n = N - j;
+          const double inv = 1.0 / double(n);
+          const double cj = a.cjd[j];
           const int cnt = EW * dimp(n);
-          const int lo = BL + lev_off(N, j) * EW * SZ, hi = BL + lev_off(N, j + 1) * EW * SZ;
-          const real ch = a.cjx_hi[j], cl = a.cjx_lo[j];
+          const int lo = BLD + lev_off(N, j) * EW * 8, hi = BLD + lev_off(N, j + 1) * EW * 8;
 #pragma unroll
           for (int s = 0; s < S3N; ++s) {
             const int item = lane + TL * s;
             if (s * TL < cnt && item < cnt) {
               const N3 x = nb3(s);
-              // c''_j / A(alpha)^2 as a pair, times the downward level R_j
-              real fh, fl, ph, pl, eh, el, t;
-              two_prod(ch, iA2[s], fh, fl);
-              fl += ch * iA2l[s] + cl * iA2[s];
-              // level 0 (the reductions' output) is a plain float: its lo array is not written
-              const real rh = at(x.self + lo), rl = j == 0 ? real(0) : at(x.self + lo + LB);
-              two_prod(fh, rh, ph, pl);
-              pl += fh * rl + fl * rh;
-              // + the integer-weighted elevation of T_{j+1}: (n - |a|) self + the e_k-lower terms
-              const real w = real(n - x.sa);
-              two_prod(w, wcar[s], eh, el);
-              two_sum(ph, eh, ph, t);
-              pl += t + el + w * wlo[s];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                two_sum(ph, at(x.dn[k] + hi), ph, t);
-                pl += t + at(x.dn[k] + hi + LB);
-              }
-              two_sum(ph, pl, wcar[s], wlo[s]);
-              at(x.self + lo) = wcar[s];
-              at(x.self + lo + LB) = wlo[s];
+              const double el = double(n - x.sa) * wd[s] +
+                                (atd(dof(x.dn[0]) + hi) + atd(dof(x.dn[1]) + hi) + atd(dof(x.dn[2]) + hi));
+              wd[s] = (cj * iA2d[s]) * atd(dof(x.self) + lo) + inv * el;
+              atd(dof(x.self) + lo) = wd[s];
             }
           }
           team_sync();
@@ -1089,7 +1058,7 @@ void stage_kernel(const StageArgs<real> a) {
 #pragma unroll
         for (int s = 0; s < S3N; ++s) {
           const int item = lane + TL * s;
-          if (item < EW * NP) acc[0][s] = aFn[s] * wcar[s] + aFn[s] * wlo[s];
+          if (item < EW * NP) acc[0][s] = real(double(aF[s]) * wd[s]);
         }
       } else {
         // downward sweep: level j = (E^{N-j+1}_{N-j})^T level j-1

@@ -231,6 +231,39 @@ def test_full_size_rhs_parity_on_sampled_elements(bb, dtype):
     assert np.all(err < tol), err
 
 
+@pytest.mark.parametrize("N", [7, 9])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_high_degree_rhs_parity_on_sampled_elements(bb, N, dtype):
+    """196,608 tets at N = 7 and 9, M = N // 2, three-layer medium: the degree-sweep
+    workload in the launch configuration it is timed in (the load placement and occupancy
+    chosen per degree and precision). The oracle recomputes the right-hand side of 200
+    sampled elements, each with its face neighbours."""
+    from workloads import c2_three_layer
+    print(f"[full-size rhs] N={N} {dtype}", flush=True)
+    M = N // 2
+    xyz, etov = kuhn_cube_mesh(32)
+    s = bb.Solver(xyz, etov, N, M, dtype=dtype)
+    medium = c2_three_layer(1)
+    s.set_c2_policy(True)  # the P^M jumps dip below zero in some elements; the arithmetic is compared
+    s.project_c2(medium)
+    q = random_state(63 + N, s.K, s.Np)
+    out = s.rhs(s.to_device(q)).double().cpu().numpy()
+    rng = np.random.default_rng(64 + N)
+    seeds = np.unique(np.concatenate([rng.choice(s.K, 196, replace=False), [0, 1, s.K - 1, s.K - 6]]))
+    nbr = s.geometry()["nbr"]
+    sub = _neighbourhood(nbr, seeds, 1)
+    o = Oracle(xyz, etov[sub], N, M)
+    o.set_c2_function(medium, project=True)
+    R = o.rhs(o.from_bernstein(q[:, sub]))
+    pos = np.searchsorted(sub, seeds)
+    a = o.bernstein_values_at_quad(out[:, seeds])
+    b = o.values_at_quad(R[:, pos])
+    wJ = o.mesh.J[pos][:, None] * o.wq[None, :]
+    err = np.sqrt(np.sum((a - b) ** 2 * wJ, axis=(1, 2)) / np.sum(b ** 2 * wJ, axis=(1, 2)))
+    tol = FP64_TOL if dtype == "f64" else fp32_tol(N)
+    assert np.all(err < tol), err
+
+
 def test_full_size_step_parity_on_sampled_elements(bb):
     """One full LSRK4 step at 196,608 tets, N=5, M=2 (FP64), Gaussian pulse, bump medium,
     each side with its own projections: after five stages an element depends on its
