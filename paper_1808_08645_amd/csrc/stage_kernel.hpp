@@ -61,6 +61,18 @@ template <typename T>
 __device__ __forceinline__ T uload(const T* p) {
   return *(const __attribute__((address_space(4))) T*)(p);
 }
+// The value of v in lane l of the wavefront (l uniform), as a scalar.
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
 
 // Graded position of (a1, a2, a3): dimp(s-1) + a3 (2s+3-a3)/2 + a2, s = a1+a2+a3.
 __host__ __device__ constexpr int g3(int a1, int a2, int a3) {
@@ -246,10 +258,35 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 #define BBW_CARRY 15
 #endif
 
-// Per-element scalars of a one-element team through scalar loads (1) or the LDS copy (0).
+// Per-element scalars (geometry, c^2) of a one-element team: from the LDS copy (0), through
+// scalar loads (1), or read across lanes from the register that staged them (2). Scalar loads
+// share their wait counter with LDS reads and return out of order, so every use of one waits
+// for all LDS reads in flight; a lane read (v_readlane) waits for nothing.
+// Per-element scalars (geometry, c^2) of a one-element team: from the LDS copy (0), through
+// scalar loads (1), or read across lanes from the register that staged them (2). Scalar
+// loads share their wait counter with LDS reads and return out of order, so every use of
+// one waits for all LDS reads in flight; a lane read (v_readlane) waits for nothing but
+// holds a few more registers. BBW_SGPR_ELEM >= 0 overrides the table.
 #ifndef BBW_SGPR_ELEM
-#define BBW_SGPR_ELEM 1
+#define BBW_SGPR_ELEM -1
 #endif
+// Product terms per batch of the table-driven product (each batch's reads are in flight
+// together, and its sum is formed before the next batch's reads are issued, which bounds
+// the registers they hold). BBW_PROD_BATCH > 0 overrides the table.
+#ifndef BBW_PROD_BATCH
+#define BBW_PROD_BATCH 0
+#endif
+// Measured at 196,608 tets, M = N/2, ms per stage, against scalar loads with one term at a
+// time (the earlier form): FP64 N = 5 lane reads 0.463 (0.470); N = 7 scalar loads, batches
+// of 2: 1.374 (1.425); N = 8 lane reads, 8: 2.158 (2.501; scalar loads 3.40); N = 9 scalar,
+// 8: 3.070 (3.473; lane reads 3.94). FP32 N = 7, 8, 9 scalar, 8: 0.813, 1.665, 2.313 (0.921,
+// 2.134, 2.921); FP32 N = 6 with lane reads lost a wave per SIMD (0.654 against 0.553).
+constexpr int scalars_table(int bytes, int N) { return bytes == 8 && (N == 5 || N == 8) ? 2 : 1; }
+constexpr int batch_table(int bytes, int N) { return bytes == 8 && N == 7 ? 2 : 8; }
+template <typename real, int N>
+constexpr int stage_scalars() { return BBW_SGPR_ELEM >= 0 ? BBW_SGPR_ELEM : scalars_table((int)sizeof(real), N); }
+template <typename real, int N>
+constexpr int stage_batch() { return BBW_PROD_BATCH > 0 ? BBW_PROD_BATCH : batch_table((int)sizeof(real), N); }
 
 // Optional occupancy target (waves per SIMD) for the register allocator; 0 leaves the
 // choice to the compiler (or to the per-instance targets below).
@@ -534,6 +571,11 @@ void stage_kernel(const StageArgs<real> a) {
   // (element k0, which exists) and their value is discarded or replaced where it is used.
   // Loads under divergent control flow would make later writes to the same registers wait
   // for all outstanding loads, which would expose the latency that the prefetch hides.
+  // Scalar r of the per-element record held by this lane. With lane reads every wave of a
+  // one-element team holds the whole record (scalars 0..PW-1 in its lanes 0..PW-1).
+  constexpr bool SC_LANES = EW == 1 && stage_scalars<real, N>() == 2;
+  static_assert(!SC_LANES || L::PW <= 64, "the per-element record must fit one wavefront");
+  auto sitem = [&](int r) { return SC_LANES ? (lane & 63) + 64 * r : lane + TL * r; };
   auto prefetch = [&](int64_t g) {
     const int64_t k0 = g * EW;
 #pragma unroll
@@ -547,7 +589,7 @@ void stage_kernel(const StageArgs<real> a) {
     }
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
-      const int i = lane + TL * r;
+      const int i = sitem(r);
       const int j = i - 25 * EW;
       const bool geo_ok = i < 25 * EW && k0 + i / 25 < K;
       const bool c2_ok = i >= 25 * EW && i < PW * EW && k0 + j / MP < K;
@@ -594,14 +636,15 @@ void stage_kernel(const StageArgs<real> a) {
   // lane keeps the value it writes at its own position when the next phase reads that
   // position again ("self" terms below): coefficient positions are the same at every degree,
   // so the value is already in the lane's registers (qcur).
-  real qcur[4][S3N];
+  real qcur[4][S3N], pcur[SPW];
   auto stage_group = [&](int64_t gg) {
     const int64_t kk = gg * EW;
 #pragma unroll
     for (int r = 0; r < SPW; ++r) {
-      const int i = lane + TL * r;
+      const int i = sitem(r);
       const bool ok = i < 25 * EW ? kk + i / 25 < K : kk + (i - 25 * EW) / MP < K;
-      if (i < PW * EW) at(wb + BP + i * SZ) = ok ? pn[r] : real(0);
+      pcur[r] = ok ? pn[r] : real(0);
+      if (i < PW * EW && (!SC_LANES || lane < 64)) at(wb + BP + i * SZ) = pcur[r];
     }
 #pragma unroll
     for (int s = 0; s < S3N; ++s) {
@@ -641,11 +684,13 @@ void stage_kernel(const StageArgs<real> a) {
     const real* const gk = a.geo + k0 * kGeoStride;
     const real* const ck = a.c2 + k0 * MP;
     auto geo_at = [&](int e, int i) -> real {
-      if constexpr (EW == 1 && BBW_SGPR_ELEM) return uload(gk + i);
+      if constexpr (SC_LANES) return lane_value(pcur[0], i);
+      else if constexpr (EW == 1 && stage_scalars<real, N>() == 1) return uload(gk + i);
       else return at(wb + BP + (e * 25 + i) * SZ);
     };
     auto c2_at = [&](int e, int b) -> real {
-      if constexpr (EW == 1 && BBW_SGPR_ELEM) return uload(ck + b);
+      if constexpr (SC_LANES) return lane_value(pcur[0], 25 + b);
+      else if constexpr (EW == 1 && stage_scalars<real, N>() == 1) return uload(ck + b);
       else return at(wb + BP + (25 * EW + e * MP + b) * SZ);
     };
     if constexpr (L::MUL_REGS) {  // keep unpacking of the product positions inside the loop
@@ -953,27 +998,26 @@ void stage_kernel(const StageArgs<real> a) {
             }
           }
         }
-      } else {  // many terms: positions from the table, beta outermost so that one c^2
-                // coefficient is live at a time (a one-element team reads it once)
-        int b = 0;
+      } else {  // many terms: positions from the table, slot by slot. A full slot has no
+                // branch and the partial last slot one branch around all of its terms, so
+                // that the table and value reads of consecutive terms can be in flight
+                // together (a branch per term would wait for each term's reads in turn).
+        auto slot_terms = [&](int s) {
+          const int item = lane + TL * s, e = item - (item / EW) * EW;
 #pragma unroll
-        for (int sb = 0; sb <= M; ++sb)
+          for (int b = 0; b < MP; ++b) {
+            const int off = wb + BR + ((int)ptab[b * (EW * NH) + item] * EW + e) * SZ;
+            h[s] += at(off) * c2_at(e, b);
+            // close a batch: its sum is formed before the next batch's reads are issued
+            constexpr int PB = stage_batch<real, N>();
+            if (b % PB == PB - 1) asm volatile("" : "+v"(h[s])::"memory");
+          }
+        };
 #pragma unroll
-          for (int b3 = 0; b3 <= sb; ++b3)
-#pragma unroll
-            for (int b2 = 0; b2 <= sb - b3; ++b2) {
-              const real cb = c2_at(0, b);
-#pragma unroll
-              for (int s = 0; s < S3; ++s) {
-                const int item = lane + TL * s;
-                if (s * TL < EW * NH && item < EW * NH) {
-                  const int e = item - (item / EW) * EW;
-                  const int off = wb + BR + ((int)ptab[b * (EW * NH) + item] * EW + e) * SZ;
-                  h[s] += at(off) * (EW == 1 ? cb : c2_at(e, b));
-                }
-              }
-              ++b;
-            }
+        for (int s = 0; s < S3; ++s) {
+          if ((s + 1) * TL <= EW * NH) slot_terms(s);
+          else if (lane + TL * s < EW * NH) slot_terms(s);
+        }
       }
 #pragma unroll
       for (int s = 0; s < S3; ++s) {
