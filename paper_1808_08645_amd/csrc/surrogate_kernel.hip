@@ -21,42 +21,80 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 }
 
 // C[m][n] (=|+=) act(sum_k A(m,k) B(k,n) + bias[n]); A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn].
-// One wavefront computes a 32 x 32 block of C as 2 x 2 MFMA tiles; a workgroup holds 4 waves
-// (a 64 x 64 block).
+// A workgroup of 4 waves computes a 64 x 64 block of C, each wave a 32 x 32 quarter as 2 x 2
+// MFMA tiles. K advances in tiles of kKT: the workgroup stages the A tile (64 x kKT) and the
+// B tile (kKT x 64) in LDS, each with loads whose consecutive threads read consecutive
+// addresses along the operand's unit-stride dimension (coalesced whichever way the operand
+// is laid out), both stored k-contiguous so that a lane's 4 consecutive k of an MFMA operand
+// are one 8-byte LDS read. The next tile's global loads are in flight while the current one
+// is multiplied.
 // With g.ksplit > 1, workgroup z sums the K range [z kc, (z+1) kc) (kc a multiple of 16) and
 // writes its raw partial block to part[z][M][N]; splitk_reduce_kernel adds the slices in order
 // and applies the epilogue.
+constexpr int kGT = 64, kKT = 32, kKP = kKT + 4;  // tile edge, K tile, padded LDS row (bf16)
+constexpr int kLoadsPerThread = kGT * kKT / 256;
+
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * 64 + (wave >> 1) * 32;
-  const int64_t n0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
-  if (m0 >= g.M || n0 >= g.N) return;
+  __shared__ __attribute__((aligned(16))) uint16_t As[kGT][kKP];  // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGT][kKP];  // [n][k]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t mb = (int64_t)blockIdx.y * kGT, nb = (int64_t)blockIdx.x * kGT;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // the wave's quarter
   const int r = lane & 15, kq = lane >> 4;
+  const int64_t kb = g.ksplit > 1 ? (int64_t)blockIdx.z * g.kc : 0;
+  const int64_t ke = g.ksplit > 1 ? (kb + g.kc < g.K ? kb + g.kc : g.K) : g.K;
+  // staging order: along k when k is the unit stride, else along the row (m or n)
+  const bool a_k = g.sak == 1, b_k = g.sbk == 1;
+  auto stage_pos = [](bool along_k, int idx, int& row, int& k) {
+    if (along_k) row = idx / kKT, k = idx % kKT;
+    else row = idx % kGT, k = idx / kGT;
+  };
+  uint16_t ra[kLoadsPerThread], rb[kLoadsPerThread];
+  auto load_tile = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < kLoadsPerThread; ++i) {
+      int row, k;
+      stage_pos(a_k, t + 256 * i, row, k);
+      const int64_t m = mb + row, ka = k0 + k;
+      ra[i] = (m < g.M && ka < ke) ? g.A[m * g.sam + ka * g.sak] : (uint16_t)0;
+      stage_pos(b_k, t + 256 * i, row, k);
+      const int64_t n = nb + row, kb2 = k0 + k;
+      rb[i] = (n < g.N && kb2 < ke) ? g.B[kb2 * g.sbk + n * g.sbn] : (uint16_t)0;
+    }
+  };
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  const int64_t kb = g.ksplit > 1 ? (int64_t)blockIdx.z * g.kc : 0;
-  const int64_t ke = g.ksplit > 1 ? (kb + g.kc < g.K ? kb + g.kc : g.K) : g.K;
-  for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-    s4 a[2], b[2];
+  if (kb < ke) load_tile(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kKT) {
+    __syncthreads();  // the previous tile's operands have been read
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int64_t m = m0 + 16 * i + r, n = n0 + 16 * i + r;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t k = k0 + 4 * kq + j;
-        const bool ka = k < ke;
-        a[i][j] = (short)((ka && m < g.M) ? g.A[m * g.sam + k * g.sak] : 0);
-        b[i][j] = (short)((ka && n < g.N) ? g.B[k * g.sbk + n * g.sbn] : 0);
-      }
+    for (int i = 0; i < kLoadsPerThread; ++i) {
+      int row, k;
+      stage_pos(a_k, t + 256 * i, row, k);
+      As[row][k] = ra[i];
+      stage_pos(b_k, t + 256 * i, row, k);
+      Bs[row][k] = rb[i];
     }
+    __syncthreads();
+    if (k0 + kKT < ke) load_tile(k0 + kKT);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int ks = 0; ks < kKT; ks += 16) {
+      s4 a[2], b[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const s4*>(&As[wm + 16 * i + r][ks + 4 * kq]);
+        b[i] = *reinterpret_cast<const s4*>(&Bs[wn + 16 * i + r][ks + 4 * kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
   }
+  const int64_t m0 = mb + wm, n0 = nb + wn;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll

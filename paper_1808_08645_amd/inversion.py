@@ -14,9 +14,12 @@ gradients come back to theta through their transposes:
 The rule that decides between them runs with the loop, from the judge's own runs: a
 surrogate round takes `inner` Adam steps on J_S and is then judged by one BBWADG forward run
 at the new theta. The round is kept when the true misfit fell and the surrogate's relative
-trace error at that theta is at most `max_err`; the first round that fails either test
-leaves theta where it was and hands the rest of the run to BBWADG gradient steps
-(backtracking on the true misfit).
+trace error at that theta is at most `max_err`. A round whose traces were within `max_err`
+but whose misfit did not fall is retried from the kept theta with a quarter of the step
+size (the surrogate is trusted there, its step was too long), at most `retries` times in a
+row; a round whose trace error exceeds `max_err`, or the last allowed retry, leaves theta
+where it was and hands the rest of the run to BBWADG gradient steps (backtracking on the
+true misfit).
 """
 from __future__ import annotations
 
@@ -124,7 +127,7 @@ class Inversion:
         J.backward()
         torch.cuda.synchronize()
         self.gradient_runs += 1
-        return float(J), th.grad.numpy().copy()
+        return float(J.detach()), th.grad.numpy().copy()
 
     def surrogate_misfit_grad(self, theta):
         """(J_S, dJ_S/dtheta) in the units of J: J_S = sigma^2 nout / 2 * mean((f - d/sigma)^2)."""
@@ -139,7 +142,7 @@ class Inversion:
         return float(np.linalg.norm(y - t) / max(np.linalg.norm(t), 1e-300))
 
     def run(self, theta0, max_time: float = 60.0, target: float = 0.0, inner: int = 40, lr: float = 0.02,
-            max_err: float = 0.2, step0: float = 0.2, max_iters: int = 1000):
+            max_err: float = 0.2, step0: float = 0.2, max_iters: int = 1000, retries: int = 2):
         """Iterate until J <= target * J(theta0), max_time seconds or max_iters iterations.
         Returns (theta, history); each history entry has the wall time t, the kept misfit J
         and what the iteration was."""
@@ -149,22 +152,26 @@ class Inversion:
         J0 = J
         hist = [{"t": 0.0, "J": J, "kind": "start"}]
         mode = "surrogate" if self.sur is not None else "bbwadg"
-        adam = (np.zeros_like(theta), np.zeros_like(theta), 0)
+        zero = (np.zeros_like(theta), np.zeros_like(theta), 0)
+        adam, lr_s, misses = zero, lr, 0
         for _ in range(max_iters):
             if time.perf_counter() - t0 >= max_time or J <= target * J0:
                 break
             if mode == "surrogate":
-                th = theta.copy()
+                th, st = theta.copy(), adam
                 for _ in range(inner):
                     _, g = self.surrogate_misfit_grad(th)
-                    th, adam = _adam(th, g, adam, lr)
+                    th, st = _adam(th, g, st, lr_s)
                 Jn, trn = self.misfit(th)
                 err = self.surrogate_error(th, trn) if trn is not None else np.inf
                 ok = bool(Jn < J and err <= max_err)
                 hist.append({"t": time.perf_counter() - t0, "J": Jn if ok else J, "kind": "surrogate round",
-                             "accepted": ok, "surrogate_err": err, "J_tried": float(Jn)})
+                             "accepted": ok, "surrogate_err": err, "J_tried": float(Jn), "lr": lr_s})
                 if ok:
-                    theta, J = th, Jn
+                    theta, J, adam, misses = th, Jn, st, 0
+                elif err <= max_err and misses < retries:
+                    misses += 1
+                    lr_s, adam = lr_s / 4.0, zero
                 else:
                     mode = "bbwadg"
                 continue
