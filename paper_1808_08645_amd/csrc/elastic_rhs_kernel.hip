@@ -170,8 +170,33 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
       const real nx = gf[1], ny = gf[2], nz = gf[3];
       for (int m = lane; m < NFP; m += 64) {
         const int po = fpos[f * NFP + m];
+        // FP64 from N = 5: the neighbour's coefficients are loaded on every face (a wall face
+        // loads its own element's as a stand-in and discards them), since loads under a branch
+        // make the compiler wait for every outstanding load where the branch joins (N = 5:
+        // 2.33 -> 1.85 ms per call at 196,608 tets). Elsewhere the branch form is kept: the
+        // extra live values cost FP32 N = 7 a wave per SIMD (2.93 -> 3.83 ms).
+        constexpr bool NB_ALWAYS = sizeof(real) == 8 && N >= 5;
         real jv[3], js[6];
-        if (cn >= 0) {
+        if constexpr (NB_ALWAYS) {
+          const bool inner = cn >= 0;
+          const int64_t k2 = inner ? (int64_t)(cn >> 2) : k;
+          const int pn = inner ? fpos[(cn & 3) * NFP + m] : po;
+          real qn[9];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) qn[c] = a.q[((size_t)c * K + k2) * NP + pn];
+          // jumps against the neighbour, or against the mirror state on a wall
+          const bool free_wall = a.wall == 0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const real own = Qs[c * NP + po];
+            jv[c] = inner ? qn[c] - own : (free_wall ? real(0) : real(-2) * own);
+          }
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const real own = Qs[(3 + c) * NP + po];
+            js[c] = inner ? qn[3 + c] - own : (free_wall ? real(-2) * own : real(0));
+          }
+        } else if (cn >= 0) {
           const int64_t k2 = cn >> 2;
           const int pn = fpos[(cn & 3) * NFP + m];
 #pragma unroll
