@@ -259,14 +259,12 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 #endif
 
 // Per-element scalars (geometry, c^2) of a one-element team: from the LDS copy (0), through
-// scalar loads (1), or read across lanes from the register that staged them (2). Scalar loads
-// share their wait counter with LDS reads and return out of order, so every use of one waits
-// for all LDS reads in flight; a lane read (v_readlane) waits for nothing.
-// Per-element scalars (geometry, c^2) of a one-element team: from the LDS copy (0), through
-// scalar loads (1), or read across lanes from the register that staged them (2). Scalar
-// loads share their wait counter with LDS reads and return out of order, so every use of
-// one waits for all LDS reads in flight; a lane read (v_readlane) waits for nothing but
-// holds a few more registers. BBW_SGPR_ELEM >= 0 overrides the table.
+// scalar loads (1), read across lanes from the register that staged them (2), or geometry
+// by lane reads and the c^2 coefficients by one batch of scalar loads at the start of the
+// product (3). Scalar loads share their wait counter with LDS reads and return out of
+// order, so every use of one waits for all LDS reads in flight; a lane read (v_readlane)
+// waits for nothing but is a vector instruction, and the product reads each coefficient
+// once per slot. BBW_SGPR_ELEM >= 0 overrides the table.
 #ifndef BBW_SGPR_ELEM
 #define BBW_SGPR_ELEM -1
 #endif
@@ -276,12 +274,14 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 #ifndef BBW_PROD_BATCH
 #define BBW_PROD_BATCH 0
 #endif
-// Measured at 196,608 tets, M = N/2, ms per stage, against scalar loads with one term at a
-// time (the earlier form): FP64 N = 5 lane reads 0.463 (0.470); N = 7 scalar loads, batches
-// of 2: 1.374 (1.425); N = 8 lane reads, 8: 2.158 (2.501; scalar loads 3.40); N = 9 scalar,
-// 8: 3.070 (3.473; lane reads 3.94). FP32 N = 7, 8, 9 scalar, 8: 0.813, 1.665, 2.313 (0.921,
-// 2.134, 2.921); FP32 N = 6 with lane reads lost a wave per SIMD (0.654 against 0.553).
-constexpr int scalars_table(int bytes, int N) { return bytes == 8 && (N == 5 || N == 8) ? 2 : 1; }
+// Measured at 196,608 tets, M = N/2, ms per stage. Against scalar loads with one product
+// term at a time (the earlier form): FP64 N = 7 scalar loads, batches of 2: 1.374 (1.425);
+// N = 8 lane reads, 8: 2.158 (2.501; scalar loads 3.40); N = 9 scalar loads, 8: 3.070
+// (3.473; lane reads 3.94); FP32 N = 7, 8, 9, 8: 0.813, 1.665, 2.313 (0.921, 2.134, 2.921).
+// Mode 3 against those: FP64 N = 4 0.313 (0.319), N = 5 0.458 (0.461, lane reads; 0.470
+// scalar loads), N = 7 1.329 (1.370), N = 9 2.985 (3.065); FP32 N = 9 2.235 (2.298), the
+// rest within 1%; FP64 N = 6 kept scalar loads (1.044 against 1.054).
+constexpr int scalars_table(int bytes, int N) { return bytes == 8 && N == 6 ? 1 : 3; }
 constexpr int batch_table(int bytes, int N) { return bytes == 8 && N == 7 ? 2 : 8; }
 template <typename real, int N>
 constexpr int stage_scalars() { return BBW_SGPR_ELEM >= 0 ? BBW_SGPR_ELEM : scalars_table((int)sizeof(real), N); }
@@ -573,7 +573,10 @@ void stage_kernel(const StageArgs<real> a) {
   // for all outstanding loads, which would expose the latency that the prefetch hides.
   // Scalar r of the per-element record held by this lane. With lane reads every wave of a
   // one-element team holds the whole record (scalars 0..PW-1 in its lanes 0..PW-1).
-  constexpr bool SC_LANES = EW == 1 && stage_scalars<real, N>() == 2;
+  constexpr bool SC_LANES = EW == 1 && stage_scalars<real, N>() >= 2;
+  // mode 3: geometry by lane reads, c^2 by one batch of scalar loads at the product's start
+  // (one wait, no lane read per coefficient and slot)
+  constexpr bool C2_BATCH = EW == 1 && stage_scalars<real, N>() == 3 && M > 0;
   static_assert(!SC_LANES || L::PW <= 64, "the per-element record must fit one wavefront");
   auto sitem = [&](int r) { return SC_LANES ? (lane & 63) + 64 * r : lane + TL * r; };
   auto prefetch = [&](int64_t g) {
@@ -688,8 +691,10 @@ void stage_kernel(const StageArgs<real> a) {
       else if constexpr (EW == 1 && stage_scalars<real, N>() == 1) return uload(gk + i);
       else return at(wb + BP + (e * 25 + i) * SZ);
     };
+    real c2s[C2_BATCH ? MP : 1];
     auto c2_at = [&](int e, int b) -> real {
-      if constexpr (SC_LANES) return lane_value(pcur[0], 25 + b);
+      if constexpr (C2_BATCH) return c2s[b];
+      else if constexpr (SC_LANES) return lane_value(pcur[0], 25 + b);
       else if constexpr (EW == 1 && stage_scalars<real, N>() == 1) return uload(ck + b);
       else return at(wb + BP + (25 * EW + e * MP + b) * SZ);
     };
@@ -982,6 +987,10 @@ void stage_kernel(const StageArgs<real> a) {
         else at(wb + BL + ((lev_off(N, lane / EW + 1) - 1) * EW + lane % EW) * SZ) = real(0);
       }
       // h_gamma = sum_beta R_{gamma-beta} c2_beta/beta!
+      if constexpr (C2_BATCH) {
+#pragma unroll
+        for (int b = 0; b < MP; ++b) c2s[b] = uload(ck + b);
+      }
       real h[S3];
 #pragma unroll
       for (int s = 0; s < S3; ++s) h[s] = real(0);
