@@ -43,10 +43,14 @@ __device__ __forceinline__ constexpr int drow(int i, int kq) { return sizeof(rea
 // w, w + kW, ...). Per tile and chunk the MFMAs are those of one wave doing both products,
 // but the R tile and the accumulators are split kW ways, so several waves per SIMD fit
 // where a wave per tile would hold a whole R tile in LDS (N >= 8) and every accumulator in
-// registers. U is double-buffered across groups, which leaves one barrier per group.
-constexpr int kW = 4;
+// registers. U is double-buffered across groups, which leaves one barrier per group. Small
+// elements have fewer output tiles than 4: then as many waves as tiles.
+template <int NP>
+constexpr int dense_waves() {
+  return (NP + 15) / 16 < 4 ? (NP + 15) / 16 : 4;
+}
 
-template <typename real, int NP>
+template <typename real, int NP, int kW = dense_waves<NP>()>
 __global__ __launch_bounds__(64 * kW)
 void wadg_dense_kernel(DenseArgs<real> a) {
   typedef typename Acc4<real>::type v4;
@@ -120,7 +124,8 @@ void wadg_dense_kernel(DenseArgs<real> a) {
 template <typename real, int NP>
 int launch_typed(const DenseArgs<real>& a, void* stream) {
   const int64_t tiles = (a.K + 15) / 16;
-  hipLaunchKernelGGL((wadg_dense_kernel<real, NP>), dim3((unsigned)tiles), dim3(64 * kW), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL((wadg_dense_kernel<real, NP>), dim3((unsigned)tiles), dim3(64 * dense_waves<NP>()), 0,
+                     (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
