@@ -6,8 +6,8 @@ oracle's quadrature points, per field, by relative L^2 norm over the mesh.
 
 Tolerances: FP64 1e-11 (relative L^2 per field), FP32 1e-5 per field at every N. The
 telescoped projection amplifies rounding by about sum |c_j| (259 and 524 at N = 8, 9 with
-M = 4); the FP32 kernels run it in float pairs from N = 8 on, which keeps those degrees
-inside the same bound.
+M = 4); the FP32 kernels run it in FP64 from N = 8 on, which keeps those degrees inside
+the same bound.
 """
 import numpy as np
 import pytest
@@ -231,10 +231,10 @@ def test_full_size_rhs_parity_on_sampled_elements(bb, dtype):
     assert np.all(err < tol), err
 
 
-@pytest.mark.parametrize("N", [7, 9])
+@pytest.mark.parametrize("N", [7, 8, 9])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_full_size_high_degree_rhs_parity_on_sampled_elements(bb, N, dtype):
-    """196,608 tets at N = 7 and 9, M = N // 2, three-layer medium: the degree-sweep
+    """196,608 tets at N = 7, 8 and 9, M = N // 2, three-layer medium: the degree-sweep
     workload in the launch configuration it is timed in (the load placement and occupancy
     chosen per degree and precision). The oracle recomputes the right-hand side of 200
     sampled elements, each with its face neighbours."""
