@@ -230,8 +230,13 @@ struct StageLayout {
   // a multi-wave team is a workgroup of its own, synchronised by the workgroup barrier
   static constexpr int TPB = TW > 1 ? 1 : cmax(1, (65536 / BYTES) < 4 ? (65536 / BYTES) : 4);
   static constexpr int WPB = TW * TPB;
-  // product positions kept in registers when they are few, computed per use otherwise
-  static constexpr bool MUL_REGS = MP * S3 <= BBW_MUL_REGS_MAX;
+  // product positions kept in registers when they are few, read from the byte table
+  // otherwise. FP64 N = 6, M = 3 (40 positions) takes the table: its 20 position registers
+  // held the instance at 184 VGPRs (2 waves per SIMD); with the table it has 149 (3 waves)
+  // and runs 0.942 against 1.047 ms per stage at 196,608 tets. Elsewhere the registers
+  // measured faster (FP64 N = 5, M = 2: 0.460 against 0.488; FP32 N = 6, M = 3: 0.550
+  // against 0.623).
+  static constexpr bool MUL_REGS = MP * S3 <= BBW_MUL_REGS_MAX && !(sizeof(real) == 8 && N == 6 && M == 3);
   static constexpr int PTAB_BYTES = MUL_REGS ? 1 : MP * EW * NH;
   // waves per SIMD that LDS allows (160 KiB per CU, 4 SIMDs); registers are budgeted for
   // the same occupancy, at most 4
