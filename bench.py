@@ -490,7 +490,7 @@ def surrogate_bench(n_models=256, n_train=224, nsteps=400, train_steps=4000, bat
     """Trace surrogate on 16^3 x 6 = 24,576 tets, N=4, M=2 (rigid walls, 64 receivers on the top
     face, Gaussian pulse at (0.5, 0.5, 0.85), nsteps steps at one dt for every medium): BBWADG
     makes the traces of n_models seeded media (FP64), the surrogate trains on n_train of them
-    (Adam, cosine learning rate 1e-3 -> 1e-5) and is judged by BBWADG on the rest."""
+    (Adam, cosine learning rate 1e-3 -> 1e-5) and is scored against BBWADG on the rest."""
     import time
 
     import torch
@@ -538,7 +538,7 @@ def surrogate_bench(n_models=256, n_train=224, nsteps=400, train_steps=4000, bat
         losses.append(sur.train_step(xd[idx], yd[idx], lr))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    # judge on the held-out media
+    # score on the held-out media
     test = np.arange(n_train, n_models)
     preds = []
     torch.cuda.synchronize()
@@ -659,7 +659,7 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=500)
     ap.add_argument("--wadg-compare-cells", type=int, default=32, help="cube cells per side for --wadg-compare")
     ap.add_argument("--surrogate", action="store_true",
-                    help="instead of the default workload: train and judge the trace surrogate (256 media)")
+                    help="instead of the default workload: train and score the trace surrogate (256 media)")
     ap.add_argument("--surrogate-media", type=int, default=256)
     ap.add_argument("--elastic", action="store_true",
                     help="instead of the default workload: elastic weight-adjusted update times, N = 2..9, M = 1, 2")

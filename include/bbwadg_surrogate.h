@@ -1,7 +1,7 @@
 /* Learned trace surrogate: a small network that maps a medium c^2, sampled on a 16^3 grid of
  * the unit cube, to the receiver traces a BBWADG run produces in it, trained on such runs
  * (data from bbwadg_misfit_gradient's forward pass). The solver stays the reference: it makes
- * the training data and judges the surrogate's error on held-out media, and a caller falls back
+ * the training data and measures the surrogate's error on held-out media, and a caller falls back
  * to it where that error is too large.
  *
  * Network (about 2 million parameters): three 3x3x3 convolutions with stride 2 and padding 1

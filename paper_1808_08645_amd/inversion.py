@@ -1,5 +1,5 @@
 """Inversion of the receiver misfit for c^2 over a few medium parameters, with the trace
-surrogate standing in for the forward solve and BBWADG as its judge and fallback.
+surrogate standing in for the forward solve and BBWADG as its check and fallback.
 
 The medium is linear in its parameters, c^2(x; theta) = sum_i theta_i phi_i(x), so both the
 weight the solver takes (the degree-M projection of c^2, a Bernstein coefficient array) and
@@ -11,8 +11,8 @@ gradients come back to theta through their transposes:
 * surrogate: J_S(theta) = 1/2 sum (sigma f(x(theta)) - d)^2 with x the normalised grid input;
   its gradient is the network's input gradient pulled back through the grid map.
 
-The rule that decides between them runs with the loop, from the judge's own runs: a
-surrogate round takes `inner` Adam steps on J_S and is then judged by one BBWADG forward run
+The rule that decides between them runs with the loop, from BBWADG's own runs: a
+surrogate round takes `inner` Adam steps on J_S and is then checked by one BBWADG forward run
 at the new theta. The round is kept when the true misfit fell and the surrogate's relative
 trace error at that theta is at most `max_err`. A round whose traces were within `max_err`
 but whose misfit did not fall is retried from the kept theta with a quarter of the step

@@ -8,7 +8,7 @@ and bumps, and the inversion starts from the mean layer value with no bumps.
 
 Both runs start from the same parameters and stop at the same misfit reduction. The gain is
 the wall time to that reduction, the surrogate's training excluded (it is paid once for any
-number of inversions in the family). Every misfit on the path is BBWADG's own (the judge), and
+number of inversions in the family). Every misfit on the path is BBWADG's own (the check), and
 every accepted surrogate round has a relative trace error at most `max_err` there."""
 import time
 
@@ -93,7 +93,7 @@ def test_surrogate_inversion_reaches_misfit_reduction_sooner(setup):
             _, hists[name] = inv.run(th0, max_time=60.0, target=TARGET, max_err=MAX_ERR)
         hs, hb = hists["surrogate"], hists["bbwadg"]
         J0 = hb[0]["J"]
-        assert hs[0]["J"] == pytest.approx(J0, rel=1e-12)  # same start, same judge
+        assert hs[0]["J"] == pytest.approx(J0, rel=1e-12)  # same start, same check
         t_sur, t_bb = _time_to(hs, TARGET * J0), _time_to(hb, TARGET * J0)
         rounds = [h for h in hs if h["kind"] == "surrogate round"]
         print(f"[inversion] seed {seed}: time to J <= {TARGET} J0: surrogate {t_sur:.3f} s "
