@@ -87,6 +87,16 @@ constexpr int elastic_waves() {
   return room >= 4 ? 4 : (room >= 1 ? room : 1);
 }
 
+// One-component groups hold their per-position table entries in registers up to this many
+// 64-position slots of the product degree (BBW_EL_REG_SLOTS forces a limit). Measured at
+// 196,608 tets against reading them from LDS in every phase: 1.1-1.55x faster for the 9-field
+// update and 1.2-1.8x for the one-field update from N = 5; FP64 N = 9, M = 4 (9 slots) was
+// 4% slower, so FP64 stops at 8 slots.
+#ifndef BBW_EL_REG_SLOTS
+#define BBW_EL_REG_SLOTS -1
+#endif
+constexpr int el_reg_slots(int bytes) { return BBW_EL_REG_SLOTS >= 0 ? BBW_EL_REG_SLOTS : (bytes == 8 ? 8 : 16); }
+
 template <typename real, int N, int M, int NC>
 struct ElasticLayout {
   static constexpr int NP = dimp(N), NH = dimp(N + M), MP = dimp(M), NB = dimp(N + M - 1);
@@ -154,20 +164,66 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
   }
   __syncthreads();
 
+  // With one component per group, item i of every phase is position i itself, so a lane
+  // visits the same positions lane + 64 s in every phase and element: their table entries
+  // and factors are read once into registers, and a phase issues only its value reads.
+  constexpr int S = (NH + 63) / 64;
+  constexpr bool REG = G == 1 && S <= el_reg_slots((int)sizeof(real));
+  uint4 es[REG ? S : 1];
+  real fh[REG ? S : 1];
+  if constexpr (REG) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int i = lane + 64 * s;
+      es[s] = i < NH ? itab[i] : uint4{0, 0, 0, 0};
+      fh[s] = i < NH ? facH[i] : real(0);
+    }
+  }
+  // 1/alpha! (a0 = N - |a| included) for the inputs, 1/beta! for the media
+  constexpr int SN = (NP + 63) / 64, SW = (L::NW * MP + 63) / 64;
+  real xinv[SN], winv[SW];
+#pragma unroll
+  for (int s = 0; s < SN; ++s) {
+    const int i = lane + 64 * s < NP ? lane + 64 * s : 0;
+    const uint4 e = itab[i];
+    const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, sa = e.w >> 8;
+    xinv[s] = real(1.0 / (factd(N - sa) * factd(a1) * factd(a2) * factd(a3)));
+  }
+#pragma unroll
+  for (int s = 0; s < SW; ++s) {
+    const int t = lane + 64 * s < L::NW * MP ? lane + 64 * s : 0;
+    const uint4 e = itab[t - (t / MP) * MP];  // beta at position b (|beta| <= M)
+    const int b1 = (e.z >> 16) & 255, b2 = e.z >> 24, b3 = e.w & 255, sb = e.w >> 8;
+    winv[s] = real(1.0 / (factd(M - sb) * factd(b1) * factd(b2) * factd(b3)));
+  }
+
+  // visits items (component cl of the group, position i < cnt) with the entry of i
+  auto items = [&](int cnt, auto&& f) {
+    if constexpr (REG) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int i = lane + 64 * s;
+        if (64 * s < cnt && i < cnt) f(0, i, s, es[s]);
+      }
+    } else {
+      for (int t = lane; t < G * cnt; t += 64) {
+        const int cl = t / cnt, i = t - cl * cnt;
+        f(cl, i, 0, itab[i]);
+      }
+    }
+  };
+
   // one reduction (E^n_{n-1})^T over G components: y_a = [(a0+1) x_a + sum_j (a_j+1) x_{a+e_j}] / n,
   // in the source's precision (stored in the destination's)
   auto reduce = [&](const auto* src, int sst, auto* dst, int dstr, int n) {
     using T = std::remove_cv_t<std::remove_pointer_t<decltype(src)>>;
-    const int cnt = dimp(n - 1);
     const T inv = T(1) / T(n);
-    for (int t = lane; t < G * cnt; t += 64) {
-      const int cl = t / cnt, i = t - cl * cnt;
-      const uint4 e = itab[i];
+    items(dimp(n - 1), [&](int cl, int i, int, const uint4 e) {
       const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - 1 - (int)(e.w >> 8);
       const T* x = src + cl * sst;
       const int u1 = e.x & 0xFFFF, u3 = e.x >> 16;
       dst[cl * dstr + i] = inv * (T(a0 + 1) * x[i] + T(a1 + 1) * x[u1] + T(a2 + 1) * x[u1 + 1] + T(a3 + 1) * x[u3]);
-    }
+    });
     wsync();
   };
 
@@ -175,25 +231,28 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
   for (int64_t k = (int64_t)blockIdx.x * WPB + wave; k < a.K; k += stride) {
     // inputs scaled by 1/alpha! (a0 = N - |a| included), the trace of the normal stresses, and
     // the media scaled by 1/beta!
-    for (int i = lane; i < NP; i += 64) {
-      const uint4 e = itab[i];
-      const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, sa = e.w >> 8;
-      const real inv = real(1.0 / (factd(N - sa) * factd(a1) * factd(a2) * factd(a3)));
-      real tr = real(0);
 #pragma unroll
-      for (int f = 0; f < NC; ++f) {
-        const real x = a.r[((size_t)f * a.K + k) * NP + i] * inv;
-        X[f * NP + i] = x;
-        if (f >= 3 && f < 6) tr += x;
+    for (int s = 0; s < SN; ++s) {
+      const int i = lane + 64 * s;
+      if (i < NP) {
+        real tr = real(0);
+#pragma unroll
+        for (int f = 0; f < NC; ++f) {
+          const real x = a.r[((size_t)f * a.K + k) * NP + i] * xinv[s];
+          X[f * NP + i] = x;
+          if (f >= 3 && f < 6) tr += x;
+        }
+        if constexpr (NC == 9) X[9 * NP + i] = tr;
       }
-      if constexpr (NC == 9) X[9 * NP + i] = tr;
     }
-    for (int t = lane; t < L::NW * MP; t += 64) {
-      const int w = t / MP, b = t - w * MP;
-      const real* src = w == 0 ? a.rho_inv : (w == 1 ? a.lam : a.mu);
-      const uint4 e = itab[b];  // beta at position b (|beta| <= M)
-      const int b1 = (e.z >> 16) & 255, b2 = e.z >> 24, b3 = e.w & 255, sb = e.w >> 8;
-      Wt[t] = src[(size_t)k * MP + b] * real(1.0 / (factd(M - sb) * factd(b1) * factd(b2) * factd(b3)));
+#pragma unroll
+    for (int s = 0; s < SW; ++s) {
+      const int t = lane + 64 * s;
+      if (t < L::NW * MP) {
+        const int w = t / MP, b = t - w * MP;
+        const real* src = w == 0 ? a.rho_inv : (w == 1 ? a.lam : a.mu);
+        Wt[t] = src[(size_t)k * MP + b] * winv[s];
+      }
     }
     wsync();
     for (int c0 = 0; c0 < NC; c0 += G) {
@@ -201,8 +260,8 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
       // lambda tr + 2 mu sigma_i, shear stresses mu sigma_s
       real* const P = M > 0 ? A : LV;  // with M = 0 the product is level 0 itself
       const int pst = M > 0 ? NH : LEV;
-      for (int t = lane; t < G * NH; t += 64) {
-        const int cl = t / NH, i = t - cl * NH, c = c0 + cl;
+      items(NH, [&](int cl, int i, int sl, const uint4) {
+        const int c = c0 + cl;
         const int f1 = NC == 1 ? 0 : (c < 3 ? c : (c < 6 ? 9 : c));
         const real* w1 = Wt + (NC == 1 ? 0 : (c < 3 ? 0 : (c < 6 ? 1 : 2))) * MP;
         const bool two = NC == 9 && c >= 3 && c < 6;
@@ -214,8 +273,8 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
           h += X[f1 * NP + p] * w1[b];
           if (two) h += real(2) * X[c * NP + p] * Wt[2 * MP + b];
         }
-        P[cl * pst + i] = h * facH[i];
-      }
+        P[cl * pst + i] = h * (REG ? fh[sl] : facH[i]);
+      });
       wsync();
       // M reductions N+M -> N (ping-pong A <-> B, the last into level 0)
       if constexpr (M > 0) {
@@ -244,18 +303,16 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
         wsync();
 #pragma unroll
         for (int j = N - 1; j >= 0; --j) {
-          const int n = N - j, cnt = dimp(n);
+          const int n = N - j;
           const double cj = a.cjd[j], inv = 1.0 / double(n);
-          for (int t = lane; t < G * cnt; t += 64) {
-            const int cl = t / cnt, i = t - cl * cnt;
-            const uint4 e = itab[i];
+          items(dimp(n), [&](int cl, int i, int, const uint4 e) {
             const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - (int)(e.w >> 8);
             double* lo = LVD + cl * LEV + lev_base(N, j);
             const double* hi = LVD + cl * LEV + lev_base(N, j + 1);
             double el = double(a1) * hi[e.y & 0xFFFF] + double(a2) * hi[e.y >> 16] + double(a3) * hi[e.z & 0xFFFF];
             if (a0 > 0) el += double(a0) * hi[i];
             lo[i] = cj * lo[i] + inv * el;  // only this item reads lo[i]
-          }
+          });
           wsync();
         }
         for (int t = lane; t < G * NP; t += 64) {
@@ -272,18 +329,16 @@ __global__ __launch_bounds__((64 * ElasticLayout<real, N, M, NC>::WAVES)) void w
         wsync();
 #pragma unroll
         for (int j = N - 1; j >= 0; --j) {
-          const int n = N - j, cnt = dimp(n);
+          const int n = N - j;
           const real cj = a.cj[j], inv = real(1) / real(n);
-          for (int t = lane; t < G * cnt; t += 64) {
-            const int cl = t / cnt, i = t - cl * cnt;
-            const uint4 e = itab[i];
+          items(dimp(n), [&](int cl, int i, int, const uint4 e) {
             const int a1 = (e.z >> 16) & 255, a2 = e.z >> 24, a3 = e.w & 255, a0 = n - (int)(e.w >> 8);
             real* lo = LV + cl * LEV + lev_base(N, j);
             const real* hi = LV + cl * LEV + lev_base(N, j + 1);
             real el = real(a1) * hi[e.y & 0xFFFF] + real(a2) * hi[e.y >> 16] + real(a3) * hi[e.z & 0xFFFF];
             if (a0 > 0) el += real(a0) * hi[i];
             lo[i] = cj * lo[i] + inv * el;  // only this item reads lo[i]
-          }
+          });
           wsync();
         }
       }
