@@ -43,9 +43,10 @@ __host__ __device__ constexpr int lev_base(int N, int j) {  // start of level j 
   return t;
 }
 
-// Components are processed in groups of G (9, 3 or 1, the largest whose buffers fit): every
-// phase of the projection runs over G x (coefficients) items at once, so a wavefront syncs
-// (1 + M + 2N) times per group instead of per component and the small levels fill more lanes.
+// Components are processed in groups of G (up to N = 4 9, 3 or 1, the largest whose buffers
+// fit; from N = 5 always 1): every phase of the projection runs over G x (coefficients) items
+// at once, so a wavefront syncs (1 + M + 2N) times per group instead of per component and the
+// small levels fill more lanes.
 template <typename real, int N, int M>
 constexpr int elastic_tables() {  // product positions (bytes), stencil table (16 B), gamma! kappa
   return dimp(M) * dimp(N + M) + 16 * dimp(N + M) + (int)sizeof(real) * dimp(N + M);
@@ -78,7 +79,11 @@ constexpr int elastic_group() {
     const int w = elastic_per_wave<real, N, M, NC>(G);
     return w <= BBW_EL_WAVE_BYTES && w + T <= 61440;
   };
-  return NC == 1 ? 1 : (fits(9) ? 9 : (fits(3) ? 3 : 1));
+  // From N = 5 one component per group, whose table entries sit in registers (below), beats
+  // wider groups whatever the LDS allows: FP32 N = 5, M = 1..3 took 0.77 / 1.23 / 2.45 ms
+  // against 0.86 / 1.62 / 3.41 with groups of 3 (196,608 tets); up to N = 4 the groups win
+  // (N = 2, M = 1: 0.21 ms against 0.50 in FP64).
+  return NC == 1 || N >= 5 ? 1 : (fits(9) ? 9 : (fits(3) ? 3 : 1));
 }
 template <typename real, int N, int M, int NC>
 constexpr int elastic_waves() {
