@@ -286,9 +286,9 @@ __device__ inline int face_pos(int f, int b0, int b1, int b2) {
 // Mode 3 against those: FP64 N = 4 0.313 (0.319), N = 5 0.458 (0.461, lane reads; 0.470
 // scalar loads), N = 6 0.924 (0.943, scalar loads), N = 7 1.329 (1.370), N = 9 2.985
 // (3.065); FP32 N = 9 2.235 (2.298), the rest within 1%. Batches of 4 for FP64 N = 7 and 8
-// (with mode 3): 1.250 and 2.112 against 1.335 (2) and 2.154 (8); FP64 N = 6 and 9 and FP32
-// N = 7..9 are fastest with 8 (FP64 N = 6 with scalar loads: 0.943 / 0.956 / 1.001 with
-// 8 / 4 / 2).
+// (with mode 3): 1.250 and 2.112 against 1.335 (2; 1.534 with 8) and 2.154 (8); FP64 N = 6
+// and 9 and FP32 N = 7..9 are fastest with 8 (FP64 N = 6 with scalar loads: 0.943 / 0.956 /
+// 1.001 with 8 / 4 / 2).
 constexpr int batch_table(int bytes, int N) { return bytes == 8 && (N == 7 || N == 8) ? 4 : 8; }
 template <typename real, int N>
 constexpr int stage_scalars() { return BBW_SGPR_ELEM >= 0 ? BBW_SGPR_ELEM : 3; }  // mode 3 at every degree
