@@ -152,8 +152,9 @@ enum { kLoadsEarly = 0, kLoadsLate = 1, kLoadsLds = 2 };
 #define BBW_LOADS -1
 #endif
 // Measured (196,608 tets, M = N/2, ms per stage, early / late / LDS): FP64 N=5 0.467 / 0.489 /
-// 0.481, N=7 1.74 / 1.42, N=8 4.16 / 2.49, N=9 4.58 / 3.46; FP32 within 2% of each other at
-// N <= 4 and early fastest from N = 5 (0.272 / 0.278 / 0.281 at N = 5).
+// 0.481, N=6 0.926 / 0.949, N=7 1.74 / 1.42, N=8 4.16 / 2.49, N=9 4.58 / 3.46; FP32 within 2%
+// of each other at N <= 4 and early fastest from N = 5 (0.272 / 0.278 / 0.281 at N = 5; N = 6
+// to 9 early / late 0.552 / 0.566, 0.809 / 0.841, 1.647 / 1.704, 2.239 / 2.307).
 constexpr int loads_table(int bytes, int N, int TW) {
   (void)TW;
   return (bytes == 8 && N >= 7) ? kLoadsLate : kLoadsEarly;
