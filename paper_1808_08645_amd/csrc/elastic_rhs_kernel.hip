@@ -27,6 +27,20 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Degree s = b1 + b2 of face position m in the graded order, m = s (s + 1) / 2 + b2, from a
+// square root: floor((sqrt(8 m + 1.5) - 1) / 2) is s with a margin of at least 0.006 on
+// either side for m < 64 (the 0.5 added under the root keeps the triangular numbers, where
+// 8 m + 1 is a perfect square, clear of the rounding of v_sqrt_f32). A few VALU instructions
+// instead of an LDS table read before the values a lift phase needs. The empty asm keeps
+// the decode where it is used: hoisted out of the face loop, the decodes of every level
+// would stay live in registers across it. Used from N = 6 (196,608 tets, ms per right-hand
+// side, table / decode: FP64 N = 9 17.3 / 11.9, N = 6..8 and FP32 N = 6..9 within 1.2%
+// either way); up to N = 5 the table read measured 1.5-6% faster and is kept there.
+__device__ __forceinline__ int face_degree(int m) {
+  asm volatile("" : "+v"(m));
+  return (int)((__builtin_amdgcn_sqrtf(8.0f * (float)m + 1.5f) - 1.0f) * 0.5f);
+}
+
 // l_i = (-1)^i C(N, i) / (i + 1): factor of lift level i.
 __host__ __device__ constexpr double lift_level(int N, int i) {
   double c = 1.0;
@@ -47,7 +61,8 @@ struct ElRhsLayout {
   static constexpr int OFF_Q = 0, OFF_R = 9 * NP, OFF_W = REG ? 9 * NP : 18 * NP, RJ = (9 * NP + 63) / 64;
   static constexpr int WSZ = 9 * NQ > 9 * (NFP + NP) ? 9 * NQ : 9 * (NFP + NP);
   static constexpr int TOTAL = OFF_W + WSZ;
-  static constexpr int TABLES = 16 * NP + 4 * NP + 4 * 4 * NFP + 4 * NFP;
+  static constexpr bool DECODE = N >= 6;  // face positions decoded (face_degree), else a table
+  static constexpr int TABLES = 16 * NP + 4 * NP + 4 * 4 * NFP + (DECODE ? 0 : 4 * NFP);
   static constexpr int per = TOTAL * (int)sizeof(real);
   static constexpr int WAVES = (61440 - TABLES) / per >= 4 ? 4 : ((61440 - TABLES) / per >= 1 ? (61440 - TABLES) / per : 1);
 };
@@ -60,7 +75,7 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
   __shared__ uint4 itab[NP];
   __shared__ uint32_t lpos[NP];  // byte f: chain position of coefficient i for face f
   __shared__ int fpos[4 * NFP];
-  __shared__ int ftab[NFP];      // face position m at any degree: s | b2 << 8 (s = b1 + b2)
+  __shared__ int ftab[L::DECODE ? 1 : NFP];  // face position m at any degree: s | b2 << 8
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   real* const Qs = smem + wave * L::TOTAL + L::OFF_Q;
   real* const Rs = smem + wave * L::TOTAL + L::OFF_R;  // used only without REG
@@ -100,11 +115,23 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
     lpos[i] = lp;
   }
   for (int i = threadIdx.x; i < 4 * NFP; i += 64 * WPB) fpos[i] = a.fpos[i];
-  for (int m = threadIdx.x; m < NFP; m += 64 * WPB) {
-    int sb = 0;
-    while ((sb + 1) * (sb + 2) / 2 <= m) ++sb;
-    ftab[m] = sb | ((m - sb * (sb + 1) / 2) << 8);
+  if constexpr (!L::DECODE) {
+    for (int m = threadIdx.x; m < NFP; m += 64 * WPB) {
+      int sb = 0;
+      while ((sb + 1) * (sb + 2) / 2 <= m) ++sb;
+      ftab[m] = sb | ((m - sb * (sb + 1) / 2) << 8);
+    }
   }
+  // degree sb and b2 of face position b (b1 = sb - b2)
+  auto face_sb = [&](int b, int& sb, int& b2) {
+    if constexpr (L::DECODE) {
+      sb = face_degree(b);
+      b2 = b - sb * (sb + 1) / 2;
+    } else {
+      sb = ftab[b] & 255;
+      b2 = ftab[b] >> 8;
+    }
+  };
   __syncthreads();
 
   // the terms of the 9 outputs: (field, direction) pairs, up to 3 per output
@@ -245,7 +272,9 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
       //   (E y)_b = (1/N) [(N - |b|) y_b + b1 y_{b-e1} + b2 y_{b-e2}]
       for (int t = lane; t < 9 * NFP; t += 64) {
         const int c = t / NFP, b = t - c * NFP;
-        const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
+        int sb, b2;
+        face_sb(b, sb, b2);
+        const int b1 = sb - b2;
         const real* F = Fs + c * NFP;
         auto etf = [&](int x, int sx, int x2) {  // N (E^T F)_x
           return real(N - sx) * F[x] + real(sx - x2 + 1) * F[x + sx + 1] + real(x2 + 1) * F[x + sx + 2];
@@ -265,7 +294,9 @@ __global__ __launch_bounds__((64 * ElRhsLayout<real, N>::WAVES)) void elastic_rh
         const real sc = real(lift_level(N, i) / lift_level(N, i - 1) / n);
         for (int t = lane; t < 9 * cnt; t += 64) {
           const int c = t / cnt, b = t - c * cnt;
-          const int sb = ftab[b] & 255, b2 = ftab[b] >> 8, b1 = sb - b2;
+          int sb, b2;
+          face_sb(b, sb, b2);
+          const int b1 = sb - b2;
           const real* C = Cs + c * NP + src;
           Cs[c * NP + dst + b] = sc * (real(n - sb) * C[b] + real(b1 + 1) * C[b + sb + 1] + real(b2 + 1) * C[b + sb + 2]);
         }
