@@ -150,16 +150,49 @@ def test_semidiscrete_energy_identity(N, M, bc, tau):
     assert abs(lhs - rhs) < 1e-12 * scale
 
 
-@pytest.mark.parametrize("N,M", [(2, 1), (4, 2), (5, 2)])
-def test_weight_adjusted_step_is_mass_inverse_times_weighted_mass(N, M):
-    """W dp/dt = M r_p with W = M M_{c^2}^{-1} M: the step applies M^{-1} M_{c^2}."""
+def _bernstein_product_integrals(N, M, c2):
+    """Reference-element integrals of Bernstein products in closed form, without quadrature:
+    int B^N_a B^N_b = |T| 3! (N!)^2 / (2N+3)! (a+b)!/(a! b!) and
+    int B^N_a B^N_b B^M_g = |T| 3! (N!)^2 M! / (2N+M+3)! (a+b+g)!/(a! b! g!)
+    (multi-index factorials over the four barycentric components; the factor |T| 3! is left
+    out, it is common to both). Returns the mass matrix [Np, Np] and the c^2-weighted mass
+    matrices [K, Np, Np] for Bernstein coefficients c2 [K, Mp] of degree M."""
+    A, G = multi_indices(N), multi_indices(M)
+
+    def mf(k):
+        return float(np.prod([factorial(x) for x in k]))
+
+    def add(*ks):
+        return tuple(sum(v) for v in zip(*ks))
+
+    Mb = np.array([[mf(add(a, b)) / (mf(a) * mf(b)) for b in A] for a in A])
+    Mb *= factorial(N) ** 2 / factorial(2 * N + 3)
+    T3 = np.array([[[mf(add(a, b, g)) / (mf(a) * mf(b) * mf(g)) for g in G] for b in A] for a in A])
+    T3 *= factorial(N) ** 2 * factorial(M) / factorial(2 * N + M + 3)
+    return Mb, np.einsum("abg,kg->kab", T3, c2)
+
+
+@pytest.mark.parametrize("N,M", [(2, 1), (4, 2), (5, 2), (3, 3)])
+def test_weight_adjusted_step_against_closed_form_bernstein_integrals(N, M):
+    """W dp/dt = M r_p with W = M M_{c^2}^{-1} M, i.e. M dp = M_{c^2} r_p: the oracle's step
+    (orthonormal basis, quadrature) against both mass matrices written out in the Bernstein
+    basis from the closed-form simplex integrals of Bernstein products. A rule not exact to
+    degree 2N+M, c^2 taken at the wrong points or a wrong projection all break it."""
     o, Q = _setup(N, M)
+    c2 = random_c2_coefficients(1, o.mesh.K, dimp(M))  # the weight _setup installs
     pre = o.rhs(Q, pre_wadg=True)[0]
     dp = o.rhs(Q)[0]
-    Mc = np.einsum("qi,kq,qj->kij", o.Vq, o.c2q * o.wq[None, :], o.Vq)
-    lhs = np.einsum("kij,kj->ki", Mc, pre)
-    rhs = dp @ o.Mref
-    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(lhs).max()
+    to_bern = np.linalg.inv(o.from_bernstein(np.eye(o.Np)))  # orthonormal -> Bernstein (rows)
+    pre_b, dp_b = pre @ to_bern, dp @ to_bern
+    Mb, Mc = _bernstein_product_integrals(N, M, c2)
+    lhs = dp_b @ Mb  # Mb is symmetric
+    rhs = np.einsum("kab,kb->ka", Mc, pre_b)
+    assert np.abs(lhs - rhs).max() < 1e-10 * np.abs(rhs).max()
+    # the check sees the weight: one Bernstein coefficient of c^2 dropped breaks it
+    c2_drop = c2.copy()
+    c2_drop[:, -1] = 0.0
+    rhs_drop = np.einsum("kab,kb->ka", _bernstein_product_integrals(N, M, c2_drop)[1], pre_b)
+    assert np.abs(lhs - rhs_drop).max() > 1e-4 * np.abs(rhs).max()
 
 
 @pytest.mark.parametrize("N", [2, 4])
