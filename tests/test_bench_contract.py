@@ -33,3 +33,18 @@ def test_committed_traffic_matches_the_kernel_source():
         ratio = t["bytes_per_launch_" + dt] / alg
         assert 1.0 <= ratio < 1.5, (dt, ratio)  # measured at or above the algorithmic bytes
         assert bench.measured_traffic(dt) == t["bytes_per_launch_" + dt]
+
+
+def test_stage_kernel_profiles_name_the_current_source():
+    """Every stage-kernel profile summary states the hash of the source it was taken on; a
+    summary left from another source would quote times and counters of a different kernel.
+    (The first design's summary, `*_baseline.md`, is a record of that design on purpose.)"""
+    import re
+    names = sorted(n for n in os.listdir(os.path.join(ROOT, "profiles")) if n.startswith("stage_kernel_"))
+    summaries = [n for n in names if n.endswith(".md") and not n.endswith("_baseline.md")]
+    assert summaries
+    for n in summaries:
+        with open(os.path.join(ROOT, "profiles", n)) as fh:
+            m = re.search(r"Kernel code sha256\[:16\] = ([0-9a-f]{16})", fh.read())
+        assert m, n
+        assert m.group(1) == bench.kernel_source_hash(), n
